@@ -1,0 +1,820 @@
+/*
+ * FP64 CPU oracle of the gradient-based-reconstruction (MEG6 + alpha-damping)
+ * right-hand side on periodic generalized-curvilinear, optionally moving,
+ * grids, after Chandravamsi, Chamarthi, Hoffmann and Frankel (arXiv 2303.10785).
+ *
+ * TEST INFRASTRUCTURE ONLY: this is the plain, slow, obviously-correct
+ * reference that the HIP product path is checked against. Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it. It shares no
+ * code, header or table with the HIP path.
+ *
+ * Style: scalar loops in the order the paper states the steps; no blocking, no
+ * fusion beyond what the equations say. Built with -O2 -ffp-contract=off and
+ * no fast-math. OpenMP (if enabled) only splits independent cells.
+ *
+ * Readings of points the paper leaves open (each is also listed in the design
+ * notes of the repository):
+ *  - Eq. E6_grads and the composite stencil of Sec. 7 fix the E6 gradient as a
+ *    difference formula, 3/4 (f[i+1]-f[i-1]) - 3/20 (f[i+2]-f[i-2]) + 1/60 (...).
+ *  - The van Leer polynomial is used in its simplified form with 1/12 on the
+ *    second derivative (Eq. vanleer-poly); the composite stencil pins this.
+ *  - The averaged state for the eigenvectors is the arithmetic mean of rho and
+ *    p of the two cells; a = sqrt(gamma p / rho).                 [unpinned]
+ *  - MP limiter constants alpha = beta = 4 (Suresh & Huynh); the right state
+ *    is the mirror image of the left-state procedure of App. E.   [unpinned]
+ *  - HLLC branch order at ties: S_L >= 0 -> F_L; else S* >= 0 -> F*L; else
+ *    S_R >= 0 -> F*R; else F_R.
+ *  - Viscous tangential face derivatives: average of the two cell gradients
+ *    (the damping term of Eq. AD-eqn1 only applies to the normal one). T uses
+ *    E6 like the other gradients.                                 [unpinned]
+ *  - Non-dimensional state: p = rho T / (gamma Mref^2), mu = Sutherland(T)/Re,
+ *    kappa = mu / ((gamma - 1) Mref^2 Pr).
+ *  - Shock sensor (not in the paper): Ducros theta = div^2 / (div^2 + |curl|^2
+ *    + 1e-30); a face takes the limited path if max(theta_i, theta_i+1) > theta_c.
+ *  - GCL: (1/J)_t = -sum_d Delta_d (I_d hat(d)_t), the hatted temporal metric
+ *    interpolated to faces with the same central scheme (Eq. Jacb2).
+ *  - Time step: CFL * min over cells and directions of 1/(|U|+c|grad d|), and
+ *    for viscous runs also (1/alpha_d) min 1/(nu |grad d|^2), nu = mu/rho.
+ *  - RK3 advances Q with L(Q) = J (Res - (1/J)_t Q) (App. B, Eq. time-split);
+ *    moving-grid metrics are evaluated once per step at t^n.
+ */
+#include "gbr_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* indexing and periodic neighbours                                         */
+/* ------------------------------------------------------------------------ */
+static long ncell_of(const ref_cfg *g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
+
+static long cell_index(const ref_cfg *g, const int ijk[3])
+{
+    return ijk[0] + (long)g->n[0] * (ijk[1] + (long)g->n[1] * ijk[2]);
+}
+
+/* Neighbour m steps along direction d of cell ijk: returns its linear index
+ * and the number of times the index wrapped (negative when going below 0). */
+static long neighbour(const ref_cfg *g, const int ijk[3], int d, int m, int *wraps)
+{
+    int t[3] = {ijk[0], ijk[1], ijk[2]};
+    int n = g->n[d];
+    int a = t[d] + m;
+    int r = a % n;
+    if (r < 0) r += n;
+    if (wraps) *wraps = (a - r) / n;
+    t[d] = r;
+    return cell_index(g, t);
+}
+
+static void unpack(const ref_cfg *g, long idx, int ijk[3])
+{
+    ijk[0] = (int)(idx % g->n[0]);
+    ijk[1] = (int)((idx / g->n[0]) % g->n[1]);
+    ijk[2] = (int)(idx / ((long)g->n[0] * g->n[1]));
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1-D stencils of Sec. 5.1 (Step-1) and Sec. 7                             */
+/* Each takes a pointer to the centre of a window of consecutive values.    */
+/* ------------------------------------------------------------------------ */
+
+/* E6 first derivative at the window centre (Eq. E6_grads, differences). */
+static double e6(const double *v)
+{
+    return 0.75 * (v[1] - v[-1]) - (3.0 / 20.0) * (v[2] - v[-2]) + (1.0 / 60.0) * (v[3] - v[-3]);
+}
+
+/* Hermite second derivative at the centre from values and first derivatives
+ * (Step-1 of Sec. 5.1): 2 (v+1 - 2 v + v-1) - (g+1 - g-1) / 2. */
+static double hermite(const double *v, const double *gv)
+{
+    return 2.0 * (v[1] - 2.0 * v[0] + v[-1]) - 0.5 * (gv[1] - gv[-1]);
+}
+
+/* Central interface value at +1/2 of the window centre: the average of the
+ * unlimited left- and right-biased states of Eq. vanleer-poly (Eq. FP-interp,
+ * Eq. interp-formulae). Needs v[-4 .. 5]. */
+static double face_central(const double *v)
+{
+    double gv[4], h[2];
+    for (int m = -1; m <= 2; ++m) gv[m + 1] = e6(v + m);
+    h[0] = hermite(v, gv + 1);
+    h[1] = hermite(v + 1, gv + 2);
+    double left = v[0] + 0.5 * gv[1] + h[0] / 12.0;
+    double right = v[1] - 0.5 * gv[2] + h[1] / 12.0;
+    return 0.5 * (left + right);
+}
+
+/* Derivative at the centre as the difference of the two central interface
+ * values (Eq. FP-interp2). Needs v[-5 .. 5]. */
+static double dcomp(const double *v) { return face_central(v) - face_central(v - 1); }
+
+/* ------------------------------------------------------------------------ */
+/* line wrappers exported for the stencil pins                              */
+/* v[0..n-1] periodic with v[i+n] = v[i] + shift                            */
+/* ------------------------------------------------------------------------ */
+static void line_window(const double *v, int n, double shift, int i, int lo, int hi, double *w)
+{
+    for (int m = lo; m <= hi; ++m) {
+        int a = i + m, r = a % n;
+        if (r < 0) r += n;
+        w[m - lo] = v[r] + (double)((a - r) / n) * shift;
+    }
+}
+
+void ref_line_e6(const double *v, int n, double shift, double *out)
+{
+    double w[7];
+    for (int i = 0; i < n; ++i) { line_window(v, n, shift, i, -3, 3, w); out[i] = e6(w + 3); }
+}
+
+void ref_line_hermite(const double *v, int n, double shift, double *out)
+{
+    double w[9], gv[3];
+    for (int i = 0; i < n; ++i) {
+        line_window(v, n, shift, i, -4, 4, w);
+        for (int m = -1; m <= 1; ++m) gv[m + 1] = e6(w + 4 + m);
+        out[i] = hermite(w + 4, gv + 1);
+    }
+}
+
+void ref_line_face(const double *v, int n, double shift, double *out)
+{
+    double w[10];
+    for (int i = 0; i < n; ++i) { line_window(v, n, shift, i, -4, 5, w); out[i] = face_central(w + 4); }
+}
+
+void ref_line_dcomp(const double *v, int n, double shift, double *out)
+{
+    double w[11];
+    for (int i = 0; i < n; ++i) { line_window(v, n, shift, i, -5, 5, w); out[i] = dcomp(w + 5); }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Metrics (Sec. 4, Sec. 7)                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Coordinate c of the periodic extension at neighbour m along d of a cell. */
+static double coord_ext(const ref_cfg *g, const double *xyz, const int ijk[3], int d, int m, int c)
+{
+    int wraps;
+    long nb = neighbour(g, ijk, d, m, &wraps);
+    return xyz[c * ncell_of(g) + nb] + (double)wraps * g->off[d][c];
+}
+
+/* Window of a periodic cell field along d (no shift). */
+static void field_window(const ref_cfg *g, const double *f, const int ijk[3], int d, int lo, int hi, double *w)
+{
+    for (int m = lo; m <= hi; ++m) w[m - lo] = f[neighbour(g, ijk, d, m, NULL)];
+}
+
+/* Conservative metrics of Thomas & Lombard (Eq. GCL_metrics) discretised with
+ * the central derivative of Sec. 7, their Jacobian (Eq. Jac-matrix), the
+ * interface values (Eq. interp-formulae) and, on moving grids, the temporal
+ * metrics (Sec. 4.2) and the GCL rate (Eq. Jacb2).
+ * Pins: composite stencil and 3-D identity coefficients (Sec. 7), discrete
+ * metric identities, freestream on static and deforming grids.            */
+int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
+{
+    const long N = ncell_of(g);
+    double *dx = (double *)malloc(sizeof(double) * 9 * N); /* dx[(d*3+c)*N] = D_d of coord c */
+    if (!dx) return -1;
+    int bad = 0;
+
+    /* Step 1: coordinate derivatives D_d(x_c) at cell centres. */
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        double w[11];
+        unpack(g, idx, ijk);
+        for (int d = 0; d < 3; ++d)
+            for (int c = 0; c < 3; ++c) {
+                for (int q = -5; q <= 5; ++q) w[q + 5] = coord_ext(g, xyz, ijk, d, q, c);
+                dx[(d * 3 + c) * N + idx] = dcomp(w + 5);
+            }
+    }
+
+    /* Step 2: hatted metrics. For direction d and coordinate c, with (d, d1, d2)
+     * and (c, c1, c2) cyclic:  hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2].
+     * The product is formed from the periodic extension of c2 around the cell.
+     * Step 3: 1/J = det[D_d x_c]; unhatted metrics d_c = J hat(d)_c.        */
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        double w[11];
+        unpack(g, idx, ijk);
+        for (int d = 0; d < 3; ++d) {
+            int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+            for (int c = 0; c < 3; ++c) {
+                int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                for (int q = -5; q <= 5; ++q)
+                    w[q + 5] = dx[(d1 * 3 + c1) * N + neighbour(g, ijk, d2, q, NULL)]
+                               * coord_ext(g, xyz, ijk, d2, q, c2);
+                double ta = dcomp(w + 5);
+                for (int q = -5; q <= 5; ++q)
+                    w[q + 5] = dx[(d2 * 3 + c1) * N + neighbour(g, ijk, d1, q, NULL)]
+                               * coord_ext(g, xyz, ijk, d1, q, c2);
+                double tb = dcomp(w + 5);
+                m[REF_M_HAT(d, c) * N + idx] = ta - tb;
+            }
+        }
+        const double *a = dx + idx;
+#define DX(d, c) a[((d) * 3 + (c)) * N]
+        double invj = DX(0, 0) * (DX(1, 1) * DX(2, 2) - DX(1, 2) * DX(2, 1))
+                    - DX(0, 1) * (DX(1, 0) * DX(2, 2) - DX(1, 2) * DX(2, 0))
+                    + DX(0, 2) * (DX(1, 0) * DX(2, 1) - DX(1, 1) * DX(2, 0));
+#undef DX
+        if (!(invj > 0.0)) bad = 1;
+        m[REF_M_INVJ * N + idx] = invj;
+        m[REF_M_J * N + idx] = 1.0 / invj;
+        for (int d = 0; d < 3; ++d)
+            for (int c = 0; c < 3; ++c)
+                m[REF_M_UNHAT(d, c) * N + idx] = m[REF_M_HAT(d, c) * N + idx] / invj;
+    }
+    free(dx);
+
+    /* Step 4 (moving grids): hatted temporal metrics hat(d)_t = -(x_t hat(d)_x
+     * + y_t hat(d)_y + z_t hat(d)_z) and their unhatted values.             */
+    for (long idx = 0; idx < N; ++idx)
+        for (int d = 0; d < 3; ++d) {
+            double ht = 0.0;
+            if (g->moving && xyz_t)
+                ht = -(xyz_t[idx] * m[REF_M_HAT(d, 0) * N + idx]
+                       + xyz_t[N + idx] * m[REF_M_HAT(d, 1) * N + idx]
+                       + xyz_t[2 * N + idx] * m[REF_M_HAT(d, 2) * N + idx]);
+            m[REF_M_HATT(d) * N + idx] = ht;
+            m[REF_M_UNHATT(d) * N + idx] = ht * m[REF_M_J * N + idx];
+        }
+
+    /* Step 5: interface values for each family f with the central formula:
+     * the three hatted f-metrics, hatted f_t, and all nine unhatted metrics. */
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        double w[10];
+        unpack(g, idx, ijk);
+        for (int f = 0; f < 3; ++f) {
+            for (int c = 0; c < 3; ++c) {
+                field_window(g, m + REF_M_HAT(f, c) * N, ijk, f, -4, 5, w);
+                m[REF_M_FHAT(f, c) * N + idx] = face_central(w + 4);
+            }
+            field_window(g, m + REF_M_HATT(f) * N, ijk, f, -4, 5, w);
+            m[REF_M_FHATT(f) * N + idx] = face_central(w + 4);
+            for (int e = 0; e < 3; ++e)
+                for (int c = 0; c < 3; ++c) {
+                    field_window(g, m + REF_M_UNHAT(e, c) * N, ijk, f, -4, 5, w);
+                    m[REF_M_FUNHAT(f, e, c) * N + idx] = face_central(w + 4);
+                }
+        }
+    }
+
+    /* Step 6: GCL rate (1/J)_t = -sum_f [I_f hat(f)_t](+1/2) - [..](-1/2). */
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        unpack(g, idx, ijk);
+        double s = 0.0;
+        for (int f = 0; f < 3; ++f) {
+            const double *ft = m + REF_M_FHATT(f) * N;
+            s += ft[idx] - ft[neighbour(g, ijk, f, -1, NULL)];
+        }
+        m[REF_M_INVJT * N + idx] = -s;
+    }
+    return bad ? 1 : 0;
+}
+
+/* Non-freestream-preserving metrics of App. D (negative control only):
+ * hat(d)_c = (c1)_d1 (c2)_d2 - (c1)_d2 (c2)_d1 from fourth-order central
+ * derivatives (Eq. 4thorder-grads), interface values from Eq. interp-formulae
+ * with that derivative in place of E6. The printed zeta_y entry has a zeta
+ * where the cyclic pattern has xi; the cyclic form is used. Static grids. */
+static double c4(const double *v) { return (2.0 / 3.0) * (v[1] - v[-1]) - (1.0 / 12.0) * (v[2] - v[-2]); }
+
+static double face_central_c4(const double *v)
+{
+    double gv[4], h[2];
+    for (int q = -1; q <= 2; ++q) gv[q + 1] = c4(v + q);
+    h[0] = hermite(v, gv + 1);
+    h[1] = hermite(v + 1, gv + 2);
+    return 0.5 * ((v[0] + 0.5 * gv[1] + h[0] / 12.0) + (v[1] - 0.5 * gv[2] + h[1] / 12.0));
+}
+
+int ref_metrics_nonfp(const ref_cfg *g, const double *xyz, double *m)
+{
+    const long N = ncell_of(g);
+    double *dx = (double *)malloc(sizeof(double) * 9 * N);
+    if (!dx) return -1;
+    int bad = 0;
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        double w[5];
+        unpack(g, idx, ijk);
+        for (int d = 0; d < 3; ++d)
+            for (int c = 0; c < 3; ++c) {
+                for (int q = -2; q <= 2; ++q) w[q + 2] = coord_ext(g, xyz, ijk, d, q, c);
+                dx[(d * 3 + c) * N + idx] = c4(w + 2);
+            }
+    }
+    for (long idx = 0; idx < N; ++idx) {
+        const double *a = dx + idx;
+#define DX(d, c) a[((d) * 3 + (c)) * N]
+        for (int d = 0; d < 3; ++d) {
+            int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+            for (int c = 0; c < 3; ++c) {
+                int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                m[REF_M_HAT(d, c) * N + idx] = DX(d1, c1) * DX(d2, c2) - DX(d2, c1) * DX(d1, c2);
+            }
+        }
+        double invj = DX(0, 0) * (DX(1, 1) * DX(2, 2) - DX(1, 2) * DX(2, 1))
+                    - DX(0, 1) * (DX(1, 0) * DX(2, 2) - DX(1, 2) * DX(2, 0))
+                    + DX(0, 2) * (DX(1, 0) * DX(2, 1) - DX(1, 1) * DX(2, 0));
+#undef DX
+        if (!(invj > 0.0)) bad = 1;
+        m[REF_M_INVJ * N + idx] = invj;
+        m[REF_M_J * N + idx] = 1.0 / invj;
+        for (int d = 0; d < 3; ++d) {
+            for (int c = 0; c < 3; ++c)
+                m[REF_M_UNHAT(d, c) * N + idx] = m[REF_M_HAT(d, c) * N + idx] / invj;
+            m[REF_M_HATT(d) * N + idx] = 0.0;
+            m[REF_M_UNHATT(d) * N + idx] = 0.0;
+        }
+        m[REF_M_INVJT * N + idx] = 0.0;
+    }
+    free(dx);
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        double w[6];
+        unpack(g, idx, ijk);
+        for (int f = 0; f < 3; ++f) {
+            for (int c = 0; c < 3; ++c) {
+                field_window(g, m + REF_M_HAT(f, c) * N, ijk, f, -2, 3, w);
+                m[REF_M_FHAT(f, c) * N + idx] = face_central_c4(w + 2);
+            }
+            m[REF_M_FHATT(f) * N + idx] = 0.0;
+            for (int e = 0; e < 3; ++e)
+                for (int c = 0; c < 3; ++c) {
+                    field_window(g, m + REF_M_UNHAT(e, c) * N, ijk, f, -2, 3, w);
+                    m[REF_M_FUNHAT(f, e, c) * N + idx] = face_central_c4(w + 2);
+                }
+        }
+    }
+    return bad ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thermodynamics (Sec. 2)                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct { double r, u, v, w, p, T; } prim_t;
+
+static prim_t primitive(const ref_cfg *g, const double *Q, long idx)
+{
+    const long N = ncell_of(g);
+    prim_t s;
+    int nv = g->ndim + 2;
+    s.r = Q[idx];
+    s.u = Q[N + idx] / s.r;
+    s.v = Q[2 * N + idx] / s.r;
+    s.w = (nv == 5) ? Q[3 * N + idx] / s.r : 0.0;
+    double E = Q[(nv - 1) * N + idx];
+    s.p = (g->gamma - 1.0) * (E - 0.5 * s.r * (s.u * s.u + s.v * s.v + s.w * s.w));
+    s.T = g->gamma * g->Mref * g->Mref * s.p / s.r;
+    return s;
+}
+
+/* Sutherland's law, normalised to 1 at T = 1, divided by Re. */
+static double viscosity(const ref_cfg *g, double T)
+{
+    return T * sqrt(T) * (1.0 + g->suth) / (T + g->suth) / g->Re;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eigenvectors of App. A (Eq. for R and R^-1) with a unit normal.          */
+/* Pins: R R^-1 = I and R^-1 B R = diag(U - a, U, U, U, U + a) with the     */
+/* primitive-form matrix B of App. A.                                       */
+/* ------------------------------------------------------------------------ */
+void ref_eigvec(const double nrm[3], double rho, double a, double R[25], double Rinv[25])
+{
+    double nx = nrm[0], ny = nrm[1], nz = nrm[2];
+    double a2 = a * a, ra = rho * a;
+    double Rm[25] = {
+        1.0 / (2.0 * a2), nx / a2, nz / a2, -ny / a2, 1.0 / (2.0 * a2),
+        -nx / (2.0 * ra), 0.0, -ny, -nz, nx / (2.0 * ra),
+        -ny / (2.0 * ra), -nz, nx, 0.0, ny / (2.0 * ra),
+        -nz / (2.0 * ra), ny, 0.0, nx, nz / (2.0 * ra),
+        0.5, 0.0, 0.0, 0.0, 0.5};
+    double Li[25] = {
+        0.0, -nx * ra, -ny * ra, -nz * ra, 1.0,
+        nx * a2, 0.0, -nz, ny, -nx,
+        nz * a2, -ny, nx, 0.0, -nz,
+        -ny * a2, -nz, 0.0, nx, ny,
+        0.0, nx * ra, ny * ra, nz * ra, 1.0};
+    memcpy(R, Rm, sizeof Rm);
+    memcpy(Rinv, Li, sizeof Li);
+}
+
+static void matvec5(const double A[25], const double x[5], double y[5])
+{
+    for (int r = 0; r < 5; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 5; ++c) s += A[r * 5 + c] * x[c];
+        y[r] = s;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Improved MP limiter of App. E for one characteristic component, written  */
+/* for the left state at i+1/2; the right state calls it with the stencil   */
+/* reflected about i+1 (wm1 <- W[i+2], w0 <- W[i+1], wp1 <- W[i], ...).      */
+/* d* are the gradient-based curvatures d_k (= R^-1 P''_k).                 */
+/* ------------------------------------------------------------------------ */
+static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+static double minmod(double a, double b) { return 0.5 * (sgn(a) + sgn(b)) * fmin(fabs(a), fabs(b)); }
+static double min3(double a, double b, double c) { return fmin(a, fmin(b, c)); }
+static double max3(double a, double b, double c) { return fmax(a, fmax(b, c)); }
+
+double ref_mp_limit(double wm1, double w0, double wp1, double dm1, double d0,
+                    double dp1, double wface, double alpha, double beta)
+{
+    double wmp = w0 + minmod(wp1 - w0, beta * (w0 - wm1));
+    if ((wface - w0) * (wface - wmp) <= 1e-20) return wface;
+    double dm_plus = minmod(d0, dp1);   /* d^M at i+1/2 */
+    double dm_minus = minmod(dm1, d0);  /* d^M at i-1/2 */
+    double wmd = 0.5 * (w0 + wp1) - 0.5 * dm_plus;
+    double wul = w0 + alpha * (w0 - wm1);
+    double wlc = 0.5 * (3.0 * w0 - wm1) + (4.0 / 3.0) * dm_minus;
+    double wmin = fmax(min3(w0, wp1, wmd), min3(w0, wul, wlc));
+    double wmax = fmin(max3(w0, wp1, wmd), max3(w0, wul, wlc));
+    return wface + minmod(wmin - wface, wmax - wface);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inviscid flux vector (Eq. inv_fluxes) and curvilinear HLLC (Sec. 5.1.1). */
+/* nt_n = (hat xi_t, hat xi_x, hat xi_y, hat xi_z) at the interface.        */
+/* Pins: F(P, P) = F(P); textbook Cartesian HLLC for n = (1,0,0), n_t = 0;  */
+/* rotation and scaling invariance; Rankine-Hugoniot across S*.             */
+/* ------------------------------------------------------------------------ */
+void ref_euler_flux(const double P[5], const double nt_n[4], double gamma, double F[5])
+{
+    double r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
+    double U = nt_n[0] + nt_n[1] * u + nt_n[2] * v + nt_n[3] * w;
+    double E = p / (gamma - 1.0) + 0.5 * r * (u * u + v * v + w * w);
+    F[0] = r * U;
+    F[1] = r * u * U + nt_n[1] * p;
+    F[2] = r * v * U + nt_n[2] * p;
+    F[3] = r * w * U + nt_n[3] * p;
+    F[4] = (E + p) * U - nt_n[0] * p;
+}
+
+static void star_state(const double P[5], double E, double U, double SK, double Ss,
+                       const double nt_n[4], double nn, double Qs[5])
+{
+    double r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
+    double nt = nt_n[0], nx = nt_n[1], ny = nt_n[2], nz = nt_n[3];
+    double fac = r * (SK - U) / (SK - Ss);
+    Qs[0] = fac;
+    Qs[1] = fac * (nx * (Ss - nt) + (ny * ny + nz * nz) * u - ny * nx * v - nz * nx * w) / nn;
+    Qs[2] = fac * (ny * (Ss - nt) - nx * ny * u + (nx * nx + nz * nz) * v - nz * ny * w) / nn;
+    Qs[3] = fac * (nz * (Ss - nt) - nx * nz * u - ny * nz * v + (nx * nx + ny * ny) * w) / nn;
+    Qs[4] = fac * (E / r + (Ss - U) * ((Ss - nt) / nn + p / (r * (SK - U))));
+}
+
+void ref_hllc(const double PL[5], const double PR[5], const double nt_n[4], double gamma, double F[5])
+{
+    double nt = nt_n[0], nx = nt_n[1], ny = nt_n[2], nz = nt_n[3];
+    double nn = nx * nx + ny * ny + nz * nz, sn = sqrt(nn);
+    double UL = nt + nx * PL[1] + ny * PL[2] + nz * PL[3];
+    double UR = nt + nx * PR[1] + ny * PR[2] + nz * PR[3];
+    double cL = sqrt(gamma * PL[4] / PL[0]), cR = sqrt(gamma * PR[4] / PR[0]);
+    double SL = fmin(UL - cL * sn, UR - cR * sn);
+    double SR = fmax(UL + cL * sn, UR + cR * sn);
+    double Ss = (PR[0] * UR * (SR - UR) - PL[0] * UL * (SL - UL) + (PL[4] - PR[4]) * nn)
+              / (PR[0] * (SR - UR) - PL[0] * (SL - UL));
+    double FL[5], FR[5];
+    ref_euler_flux(PL, nt_n, gamma, FL);
+    ref_euler_flux(PR, nt_n, gamma, FR);
+    if (0.0 <= SL) { memcpy(F, FL, sizeof FL); return; }
+    if (0.0 >= SR) { memcpy(F, FR, sizeof FR); return; }
+    const double *P = (0.0 <= Ss) ? PL : PR;
+    const double *FK = (0.0 <= Ss) ? FL : FR;
+    double SK = (0.0 <= Ss) ? SL : SR;
+    double U = (0.0 <= Ss) ? UL : UR;
+    double E = P[4] / (gamma - 1.0) + 0.5 * P[0] * (P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
+    double QK[5] = {P[0], P[0] * P[1], P[0] * P[2], P[0] * P[3], E};
+    double Qs[5];
+    star_state(P, E, U, SK, Ss, nt_n, nn, Qs);
+    for (int q = 0; q < 5; ++q) F[q] = FK[q] + SK * (Qs[q] - QK[q]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cell gradients (Step-1, Sec. 5.1; reused by Sec. 5.2 and the sensor).    */
+/* grad[(d * 4 + s) * N + cell], s = u, v, w, T; E6 along d.                */
+/* ------------------------------------------------------------------------ */
+void ref_gradients(const ref_cfg *g, const double *Q, double *grad)
+{
+    const long N = ncell_of(g);
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        unpack(g, idx, ijk);
+        for (int d = 0; d < 3; ++d) {
+            double wu[7], wv[7], ww[7], wT[7];
+            for (int q = -3; q <= 3; ++q) {
+                prim_t s = primitive(g, Q, neighbour(g, ijk, d, q, NULL));
+                wu[q + 3] = s.u; wv[q + 3] = s.v; ww[q + 3] = s.w; wT[q + 3] = s.T;
+            }
+            grad[(d * 4 + 0) * N + idx] = e6(wu + 3);
+            grad[(d * 4 + 1) * N + idx] = e6(wv + 3);
+            grad[(d * 4 + 2) * N + idx] = e6(ww + 3);
+            grad[(d * 4 + 3) * N + idx] = e6(wT + 3);
+        }
+    }
+}
+
+/* Ducros sensor from the cell gradients and the cell (unhatted) metrics:
+ * du_a/dx_b = sum_d (d_{x_b}) du_a/dd. Not part of the paper.            */
+void ref_sensor(const ref_cfg *g, const double *m, const double *grad, double *theta)
+{
+    const long N = ncell_of(g);
+#pragma omp parallel for schedule(static)
+    for (long idx = 0; idx < N; ++idx) {
+        double G[3][3]; /* G[a][b] = d u_a / d x_b */
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    s += m[REF_M_UNHAT(d, b) * N + idx] * grad[(d * 4 + a) * N + idx];
+                G[a][b] = s;
+            }
+        double div = G[0][0] + G[1][1] + G[2][2];
+        double wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
+        double d2 = div * div;
+        theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + 1e-30);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Interface flux along direction f at the face between cell idx and its +1 */
+/* neighbour: Steps 1-6 of Sec. 5.1 and Steps 1-4 of Sec. 5.2.             */
+/* ------------------------------------------------------------------------ */
+static int face_flux(const ref_cfg *g, const double *m, const double *Q, const double *grad,
+                     const double *theta, int f, const int ijk[3], long idx, double phi[5])
+{
+    const long N = ncell_of(g);
+    /* primitives on the line, offsets -5 .. +6 about cell i */
+    double P[12][5], T[12];
+    long nb[12];
+    for (int q = -5; q <= 6; ++q) {
+        nb[q + 5] = neighbour(g, ijk, f, q, NULL);
+        prim_t s = primitive(g, Q, nb[q + 5]);
+        P[q + 5][0] = s.r; P[q + 5][1] = s.u; P[q + 5][2] = s.v; P[q + 5][3] = s.w; P[q + 5][4] = s.p;
+        T[q + 5] = s.T;
+    }
+    /* Step-1: E6 first derivatives at offsets -2..3, Hermite second at -1..2 */
+    double D1[6][5], D2[4][5];
+    for (int q = -2; q <= 3; ++q)
+        for (int s = 0; s < 5; ++s) {
+            double w[7];
+            for (int t = -3; t <= 3; ++t) w[t + 3] = P[q + t + 5][s];
+            D1[q + 2][s] = e6(w + 3);
+        }
+    for (int q = -1; q <= 2; ++q)
+        for (int s = 0; s < 5; ++s) {
+            double w[3] = {P[q + 4][s], P[q + 5][s], P[q + 6][s]};
+            double gv[3] = {D1[q + 1][s], D1[q + 2][s], D1[q + 3][s]};
+            D2[q + 1][s] = hermite(w + 1, gv + 1);
+        }
+#define PC(q) P[(q) + 5]
+#define P1(q) D1[(q) + 2]
+#define P2(q) D2[(q) + 1]
+
+    double nt_n[4] = {m[REF_M_FHATT(f) * N + idx], m[REF_M_FHAT(f, 0) * N + idx],
+                      m[REF_M_FHAT(f, 1) * N + idx], m[REF_M_FHAT(f, 2) * N + idx]};
+
+    int limited = 0;
+    if (g->limiter == REF_LIM_MP) limited = 1;
+    else if (g->limiter == REF_LIM_DUCROS)
+        limited = fmax(theta[idx], theta[nb[6]]) > g->theta_c;
+
+    double PL[5], PR[5];
+    if (limited) {
+        /* Step-2: project P, P', P'' with the left eigenvectors of the
+         * averaged state and the unit interface normal.                  */
+        double rb = 0.5 * (PC(0)[0] + PC(1)[0]);
+        double pb = 0.5 * (PC(0)[4] + PC(1)[4]);
+        double ab = sqrt(g->gamma * pb / rb);
+        double nn = sqrt(nt_n[1] * nt_n[1] + nt_n[2] * nt_n[2] + nt_n[3] * nt_n[3]);
+        double nu[3] = {nt_n[1] / nn, nt_n[2] / nn, nt_n[3] / nn};
+        double R[25], Ri[25];
+        ref_eigvec(nu, rb, ab, R, Ri);
+        double W[4][5], W1[2][5], W2[4][5];
+        for (int q = -1; q <= 2; ++q) { matvec5(Ri, PC(q), W[q + 1]); matvec5(Ri, P2(q), W2[q + 1]); }
+        for (int q = 0; q <= 1; ++q) matvec5(Ri, P1(q), W1[q]);
+        /* Step-3 and Step-4 per characteristic field. */
+        double WL[5], WR[5];
+        for (int s = 0; s < 5; ++s) {
+            double wl = W[1][s] + 0.5 * W1[0][s] + W2[1][s] / 12.0;
+            double wr = W[2][s] - 0.5 * W1[1][s] + W2[2][s] / 12.0;
+            WL[s] = ref_mp_limit(W[0][s], W[1][s], W[2][s], W2[0][s], W2[1][s], W2[2][s],
+                                 wl, g->alpha_mp, g->beta_mp);
+            WR[s] = ref_mp_limit(W[3][s], W[2][s], W[1][s], W2[3][s], W2[2][s], W2[1][s],
+                                 wr, g->alpha_mp, g->beta_mp);
+        }
+        /* Step-5: back to primitive variables. */
+        matvec5(R, WL, PL);
+        matvec5(R, WR, PR);
+    } else {
+        /* Unlimited states of Eq. vanleer-poly directly in primitive form
+         * (identical to projecting and back-projecting, as R R^-1 = I). */
+        for (int s = 0; s < 5; ++s) {
+            PL[s] = PC(0)[s] + 0.5 * P1(0)[s] + P2(0)[s] / 12.0;
+            PR[s] = PC(1)[s] - 0.5 * P1(1)[s] + P2(1)[s] / 12.0;
+        }
+    }
+    if (g->ndim == 2) { PL[3] = 0.0; PR[3] = 0.0; }
+    int bad = !(PL[0] > 0.0 && PL[4] > 0.0 && PR[0] > 0.0 && PR[4] > 0.0);
+
+    /* Step-6: HLLC. */
+    double F[5];
+    ref_hllc(PL, PR, nt_n, g->gamma, F);
+
+    double Fv[5] = {0, 0, 0, 0, 0};
+    if (g->viscous) {
+        /* Sec. 5.2, Step-1: interface gradients of (u, v, w, T). */
+        double dT[2], wT[7];
+        for (int q = 0; q <= 1; ++q) {
+            for (int t = -3; t <= 3; ++t) wT[t + 3] = T[q + t + 5];
+            dT[q] = e6(wT + 3);
+        }
+        double sc[2][4] = {{PC(0)[1], PC(0)[2], PC(0)[3], T[5]}, {PC(1)[1], PC(1)[2], PC(1)[3], T[6]}};
+        double sd[2][4] = {{P1(0)[1], P1(0)[2], P1(0)[3], dT[0]}, {P1(1)[1], P1(1)[2], P1(1)[3], dT[1]}};
+        double sL[4], sR[4], gf[3][4]; /* gf[e][s]: d s / d e at the face */
+        for (int s = 0; s < 4; ++s) {
+            sL[s] = sc[0][s] + 0.5 * sd[0][s];
+            sR[s] = sc[1][s] - 0.5 * sd[1][s];
+            gf[f][s] = 0.5 * (sd[0][s] + sd[1][s]) + 0.5 * g->alpha_d * (sR[s] - sL[s]);
+            for (int e = 0; e < 3; ++e) {
+                if (e == f) continue;
+                gf[e][s] = 0.5 * (grad[(e * 4 + s) * N + idx] + grad[(e * 4 + s) * N + nb[6]]);
+            }
+        }
+        /* Step-2: chain rule with interface unhatted metrics. */
+        double Dx[4][3]; /* Dx[s][b] = d s / d x_b */
+        for (int s = 0; s < 4; ++s)
+            for (int b = 0; b < 3; ++b) {
+                double acc = 0.0;
+                for (int e = 0; e < 3; ++e) acc += m[REF_M_FUNHAT(f, e, b) * N + idx] * gf[e][s];
+                Dx[s][b] = acc;
+            }
+        /* Step-3: stresses and heat flux at the interface. */
+        double Tf = 0.5 * (sL[3] + sR[3]);
+        double mu = viscosity(g, Tf);
+        double lam = -2.0 / 3.0 * mu;
+        double kap = mu / ((g->gamma - 1.0) * g->Mref * g->Mref * g->Pr);
+        double uf = 0.5 * (sL[0] + sR[0]), vf = 0.5 * (sL[1] + sR[1]), wf = 0.5 * (sL[2] + sR[2]);
+        double div = Dx[0][0] + Dx[1][1] + Dx[2][2];
+        double txx = 2.0 * mu * Dx[0][0] + lam * div;
+        double tyy = 2.0 * mu * Dx[1][1] + lam * div;
+        double tzz = 2.0 * mu * Dx[2][2] + lam * div;
+        double txy = mu * (Dx[0][1] + Dx[1][0]);
+        double txz = mu * (Dx[0][2] + Dx[2][0]);
+        double tyz = mu * (Dx[1][2] + Dx[2][1]);
+        double bx = uf * txx + vf * txy + wf * txz + kap * Dx[3][0];
+        double by = uf * txy + vf * tyy + wf * tyz + kap * Dx[3][1];
+        double bz = uf * txz + vf * tyz + wf * tzz + kap * Dx[3][2];
+        /* Step-4: interface viscous flux with hatted interface metrics. */
+        double hx = nt_n[1], hy = nt_n[2], hz = nt_n[3];
+        Fv[1] = hx * txx + hy * txy + hz * txz;
+        Fv[2] = hx * txy + hy * tyy + hz * tyz;
+        Fv[3] = hx * txz + hy * tyz + hz * tzz;
+        Fv[4] = hx * bx + hy * by + hz * bz;
+    }
+    for (int s = 0; s < 5; ++s) {
+        phi[s] = F[s] - Fv[s];
+        if (!isfinite(phi[s])) bad = 1;
+    }
+    return bad;
+#undef PC
+#undef P1
+#undef P2
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-hand side (Sec. 3): Res = -sum_f [Phi(+1/2) - Phi(-1/2)], the three */
+/* directions accumulated in the order xi, eta, zeta.                       */
+/* Pins: freestream, conservation, accuracy order, exact Riemann solution.  */
+/* Returns 1 if a reconstructed or cell state is non-physical.             */
+/* ------------------------------------------------------------------------ */
+int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
+{
+    const long N = ncell_of(g);
+    const int nv = g->ndim + 2;
+    const int nf = g->ndim;
+    double *grad = (double *)calloc((size_t)12 * N, sizeof(double));
+    double *theta = (double *)calloc((size_t)N, sizeof(double));
+    double *phi = (double *)malloc(sizeof(double) * 5 * N);
+    if (!grad || !theta || !phi) { free(grad); free(theta); free(phi); return -1; }
+    ref_gradients(g, Q, grad);
+    if (g->limiter == REF_LIM_DUCROS) ref_sensor(g, m, grad, theta);
+    int bad = 0;
+    for (long idx = 0; idx < N; ++idx) {
+        prim_t s = primitive(g, Q, idx);
+        if (!(s.r > 0.0 && s.p > 0.0 && isfinite(s.r) && isfinite(s.p))) bad = 1;
+    }
+    for (long idx = 0; idx < (long)nv * N; ++idx) res[idx] = 0.0;
+    for (int f = 0; f < nf && !bad; ++f) {
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            double ph[5];
+            unpack(g, idx, ijk);
+            if (face_flux(g, m, Q, grad, theta, f, ijk, idx, ph)) bad = 1;
+            for (int s = 0; s < 5; ++s) phi[s * N + idx] = ph[s];
+        }
+#pragma omp parallel for schedule(static)
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            long lo = neighbour(g, ijk, f, -1, NULL);
+            for (int v = 0; v < nv; ++v) {
+                int s = (nv == 4 && v == 3) ? 4 : v; /* 2-D: skip the w-momentum */
+                res[v * N + idx] -= phi[s * N + idx] - phi[s * N + lo];
+            }
+        }
+    }
+    free(grad);
+    free(theta);
+    free(phi);
+    return bad ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step (App. B) and SSP-RK3 stage (App. B with Eq. time-split).       */
+/* ------------------------------------------------------------------------ */
+double ref_cfl_min(const ref_cfg *g, const double *m, const double *Q)
+{
+    const long N = ncell_of(g);
+    double best = INFINITY, bestv = INFINITY;
+    for (long idx = 0; idx < N; ++idx) {
+        prim_t s = primitive(g, Q, idx);
+        double c = sqrt(g->gamma * s.p / s.r);
+        double nu = g->viscous ? viscosity(g, s.T) / s.r : 0.0;
+        for (int d = 0; d < g->ndim; ++d) {
+            double dxv = m[REF_M_UNHAT(d, 0) * N + idx], dyv = m[REF_M_UNHAT(d, 1) * N + idx];
+            double dzv = m[REF_M_UNHAT(d, 2) * N + idx];
+            double U = m[REF_M_UNHATT(d) * N + idx] + dxv * s.u + dyv * s.v + dzv * s.w;
+            double gn2 = dxv * dxv + dyv * dyv + dzv * dzv;
+            double inv = 1.0 / (fabs(U) + c * sqrt(gn2));
+            if (inv < best) best = inv;
+            if (g->viscous) {
+                double iv = 1.0 / (nu * gn2);
+                if (iv < bestv) bestv = iv;
+            }
+        }
+    }
+    if (g->viscous) {
+        double v = bestv / g->alpha_d;
+        if (v < best) best = v;
+    }
+    return best;
+}
+
+void ref_rk_stage(const ref_cfg *g, const double *m, int stage, double dt,
+                  const double *Qn, double *Q, const double *res)
+{
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+    const long N = ncell_of(g);
+    const int nv = g->ndim + 2;
+    for (int v = 0; v < nv; ++v)
+        for (long idx = 0; idx < N; ++idx) {
+            long e = v * N + idx;
+            double L = m[REF_M_J * N + idx] * (res[e] - m[REF_M_INVJT * N + idx] * Q[e]);
+            Q[e] = A[stage] * Qn[e] + B[stage] * (Q[e] + dt * L);
+        }
+}
+
+int ref_step(const ref_cfg *g, double *m, const double *xyz, const double *xyz_t,
+             double *Q, double cfl_or_dt, int dt_mode, double *dt_out)
+{
+    const long N = ncell_of(g);
+    const int nv = g->ndim + 2;
+    if (g->moving) {
+        int rc = ref_metrics(g, xyz, xyz_t, m);
+        if (rc) return rc;
+    }
+    double dt = (dt_mode == REF_DT_CFL) ? cfl_or_dt * ref_cfl_min(g, m, Q) : cfl_or_dt;
+    double *Qn = (double *)malloc(sizeof(double) * nv * N);
+    double *res = (double *)malloc(sizeof(double) * nv * N);
+    if (!Qn || !res) { free(Qn); free(res); return -1; }
+    memcpy(Qn, Q, sizeof(double) * nv * N);
+    int rc = 0;
+    for (int s = 0; s < 3 && !rc; ++s) {
+        rc = ref_rhs(g, m, Q, res);
+        if (!rc) ref_rk_stage(g, m, s, dt, Qn, Q, res);
+    }
+    free(Qn);
+    free(res);
+    if (dt_out) *dt_out = dt;
+    return rc;
+}

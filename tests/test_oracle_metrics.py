@@ -1,0 +1,181 @@
+"""Pins of the oracle's metrics and of freestream preservation (Sec. 4, Sec. 7,
+Sec. 8.1-8.2)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GAMMA = 1.4
+M = 0.5
+P_INF = 1.0 / (GAMMA * M * M)
+
+
+def _identity_residual(m, ndim=3):
+    """sum_f [I_f hat(f)_c](+1/2) - [...](-1/2) for c = x, y, z (Eq. metric-Idty)."""
+    out = []
+    for c in range(3):
+        s = np.zeros(m.shape[1:])
+        for f in range(ndim):
+            face = m[oracle.M_FHAT(f, c)]
+            s += face - np.roll(face, 1, axis=2 - f)
+        out.append(s)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.random3d((14, 12, 10), amp=0.2, seed=4),
+    lambda: W.sinusoidal3d((12, 12, 12)),
+    lambda: W.jet3d((24, 16, 14)),
+    lambda: W.Deforming3D((16, 16, 16), rand=0.2, seed=2).at(0.13),
+])
+def test_discrete_metric_identities(maker):
+    g = maker()
+    m = oracle.metrics(g)
+    scale = max(np.abs(m[oracle.M_HAT(d, c)]).max() for d in range(3) for c in range(3))
+    assert np.abs(_identity_residual(m)).max() <= 1e-13 * scale
+
+
+def test_metric_identities_2d():
+    g = W.wavy2d((24, 20), rand=0.2, seed=1)
+    m = oracle.metrics(g)
+    scale = np.abs(m[:9]).max()
+    assert np.abs(_identity_residual(m, ndim=2)).max() <= 1e-13 * scale
+
+
+def test_cartesian_grid_metrics():
+    """On a uniform Cartesian box: hat(xi)_x = dy dz, 1/J = dx dy dz, zero
+    cross terms (closed form)."""
+    g = W.uniform3d((8, 10, 12), (2.0, 3.0, 4.0))
+    m = oracle.metrics(g)
+    dx, dy, dz = 2.0 / 8, 3.0 / 10, 4.0 / 12
+    assert np.allclose(m[oracle.M_INVJ], dx * dy * dz, rtol=1e-13)
+    assert np.allclose(m[oracle.M_HAT(0, 0)], dy * dz, rtol=1e-13)
+    assert np.allclose(m[oracle.M_HAT(1, 1)], dx * dz, rtol=1e-13)
+    assert np.allclose(m[oracle.M_HAT(2, 2)], dx * dy, rtol=1e-13)
+    assert np.allclose(m[oracle.M_UNHAT(0, 0)], 1 / dx, rtol=1e-13)
+    for d in range(3):
+        for c in range(3):
+            if c != d:
+                assert np.abs(m[oracle.M_HAT(d, c)]).max() < 1e-14
+
+
+def test_affine_grid_metrics_match_inverse_jacobian():
+    """Sheared periodic grid x = A (i, j, k) (affine): metrics are the exact
+    inverse of the constant Jacobian matrix (closed form)."""
+    A = np.array([[0.3, 0.05, -0.02], [0.04, 0.25, 0.03], [-0.01, 0.02, 0.2]])
+    n = (6, 7, 8)
+    k, j, i = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    idx = np.stack([i, j, k]).reshape(3, -1).astype(float) + 0.5
+    xyz = (A @ idx).reshape(3, n[2], n[1], n[0])
+    off = np.array([A[:, 0] * n[0], A[:, 1] * n[1], A[:, 2] * n[2]])
+    g = dict(n=n, ndim=3, xyz=np.ascontiguousarray(xyz), off=off, xyz_t=None)
+    m = oracle.metrics(g)
+    # rows of A^-1 are grad(xi), grad(eta), grad(zeta)
+    Ainv = np.linalg.inv(A)
+    detA = np.linalg.det(A)
+    assert np.allclose(m[oracle.M_INVJ], detA, rtol=1e-12)
+    for d in range(3):
+        for c in range(3):
+            assert np.allclose(m[oracle.M_UNHAT(d, c)], Ainv[d, c], rtol=1e-11, atol=1e-12)
+
+
+def test_gcl_rate_tracks_volume_change():
+    """(1/J)_t from the GCL (Eq. Jacb2) approximates d(1/J)/dt of the moving
+    grid to truncation accuracy, converging under refinement (catches sign
+    and missing-term mistakes in the temporal metrics)."""
+    errs = []
+    for n in (12, 24):
+        mv = W.Deforming3D((n, n, n), L=12.0, A=0.6, nmode=2)
+        t, h = 0.07, 1e-5
+        m = oracle.metrics(mv.at(t))
+        mp = oracle.metrics(dict(mv.at(t + h), xyz_t=None))
+        mm = oracle.metrics(dict(mv.at(t - h), xyz_t=None))
+        dvol = (mp[oracle.M_INVJ] - mm[oracle.M_INVJ]) / (2 * h)
+        gcl = m[oracle.M_INVJT]
+        errs.append(np.abs(gcl - dvol).max() / np.abs(dvol).max())
+    assert errs[0] < 5e-2
+    assert errs[1] < errs[0] / 8.0
+
+
+@pytest.mark.parametrize("grid", ["sin", "rand"])
+@pytest.mark.parametrize("visc", [False, True])
+@pytest.mark.parametrize("lim", ["none", "mp", "ducros"])
+def test_freestream_static_rhs_is_roundoff(grid, visc, lim):
+    """Uniform flow on skewed static grids gives Res = 0 to round-off (Sec. 8.1.1)."""
+    g = W.sinusoidal3d((12, 12, 12)) if grid == "sin" else W.random3d((12, 12, 12), seed=7)
+    m = oracle.metrics(g)
+    Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, P_INF)
+    r = oracle.rhs(g, m, Q, viscous=visc, limiter=lim, Mref=M)
+    # flux scale: largest inviscid flux component, (E + p) |u| |metric|
+    E = P_INF / (GAMMA - 1.0) + 0.5
+    scale = (E + P_INF) * np.abs(m[:9]).max()
+    assert np.abs(r).max() <= 1e-13 * scale
+
+
+def test_freestream_moving_rhs_balances_gcl():
+    """On a deforming grid the RHS of uniform flow equals (1/J)_t Q, so that
+    dQ/dt = J (Res - (1/J)_t Q) vanishes to round-off (Sec. 8.2.1)."""
+    mv = W.Deforming3D((12, 12, 12), A=0.75, nmode=2, rand=0.2, seed=5)
+    g = mv.at(0.21)
+    m = oracle.metrics(g)
+    Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, P_INF)
+    for visc in (False, True):
+        r = oracle.rhs(g, m, Q, viscous=visc, limiter="mp", Mref=M)
+        L = m[oracle.M_J] * (r - m[oracle.M_INVJT] * Q)
+        assert np.abs(r).max() > 1e-3  # the grid motion is really felt
+        assert np.abs(L).max() <= 1e-12
+
+
+def test_freestream_moving_steps_keep_transverse_velocity_zero():
+    """Several SSP-RK3 steps on a deforming randomized grid keep v, w at
+    round-off (config: 3-D NS freestream, Mach 0.5, Re 1e4)."""
+    mv = W.Deforming3D((12, 12, 12), A=0.75, nmode=2, rand=0.2, seed=6)
+    g = mv.at(0.0)
+    m = oracle.metrics(g)
+    Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, P_INF)
+    t = 0.0
+    for _ in range(6):
+        g = mv.at(t)
+        Q, dt = oracle.step(g, m, Q, 0.2, viscous=True, limiter="mp", Mref=M, Re=1e4)
+        t += dt
+    rho, u, v, w, p = oracle.prim_from_Q(Q)
+    assert np.abs(v).max() < 1e-12 and np.abs(w).max() < 1e-12
+    assert np.abs(rho - 1).max() < 1e-12 and np.abs(p - P_INF).max() < 1e-11
+
+
+def test_nonconservative_metrics_break_freestream():
+    """Negative control (App. D): non-conservative metrics give a freestream
+    RHS far above round-off on the same grids."""
+    for g in (W.sinusoidal3d((12, 12, 12)), W.random3d((12, 12, 12), seed=7)):
+        m = oracle.metrics(g, nonfp=True)
+        Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, P_INF)
+        r = oracle.rhs(g, m, Q, limiter="mp", Mref=M)
+        assert np.abs(r).max() > 1e-4
+
+
+def _l2_vw_after(g, m, t_end, cfl=0.2):
+    Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, P_INF)
+    t = 0.0
+    while t < t_end - 1e-12:
+        dt = cfl * oracle.cfl_min(g, m, Q, Mref=M)
+        dt = min(dt, t_end - t)
+        Q, _ = oracle.step(g, m, Q, dt, dt_mode=oracle.DT_FIXED, limiter="mp", Mref=M)
+        t += dt
+    rho, u, v, w, p = oracle.prim_from_Q(Q)
+    return np.sqrt(np.mean(v * v)), np.sqrt(np.mean(w * w))
+
+
+@pytest.mark.slow
+def test_freestream_errors_match_paper_magnitudes():
+    """Sec. 8.1.1: on 20^3 grids (L = 4, M = 0.5, t = 10) the non-conservative
+    metrics leave L2 errors of order 1e-3 (sinusoidal) and 1e-1 (randomized) in
+    v and w, while the conservative metrics stay at machine zero."""
+    sin = W.sinusoidal3d((20, 20, 20))
+    rnd = W.random3d((20, 20, 20), amp=0.2, seed=11)
+    ev_sin = _l2_vw_after(sin, oracle.metrics(sin, nonfp=True), 10.0)
+    ev_rnd = _l2_vw_after(rnd, oracle.metrics(rnd, nonfp=True), 10.0)
+    assert 1e-4 < max(ev_sin) < 1e-2, ev_sin
+    assert 1e-2 < max(ev_rnd) < 1.0, ev_rnd
+    fp = _l2_vw_after(rnd, oracle.metrics(rnd), 2.0)
+    assert max(fp) < 1e-13
