@@ -1,0 +1,170 @@
+/*
+ * gbr.h - C ABI of the MI355X gradient-based-reconstruction solver.
+ *
+ * The library evaluates the semi-discrete right-hand side of the compressible
+ * Euler / Navier-Stokes equations in generalized curvilinear coordinates
+ * (Chandravamsi, Chamarthi, Hoffmann, Frankel, arXiv 2303.10785): E6 central
+ * gradients, gradient-based characteristic interface states with the improved
+ * MP limiter (optionally gated by a Ducros shock sensor), the curvilinear HLLC
+ * flux, the alpha-damping viscous flux, freestream-preserving conservative
+ * metrics and the geometric conservation law on moving grids, and the SSP-RK3
+ * stage update. All arithmetic runs in HIP kernels on the device.
+ *
+ * Conventions (all calls):
+ *  - Pointers to field data are DEVICE pointers owned by the caller, on the
+ *    device that was current when the grid was created.
+ *  - Field layout is structure-of-arrays [var][nk][nj][ni], i fastest,
+ *    FP64. Conserved variables in the order (rho, rho u, rho v, [rho w], E):
+ *    nvar = ndim + 2. Coordinates are [3][nk][nj][ni] (x, y, z); for ndim = 2
+ *    the z plane is ignored and z is taken as the zeta index.
+ *  - Every grid is periodic in every direction; off[d] is the (x, y, z)
+ *    shift of the coordinates when the index along direction d wraps once.
+ *  - Work is enqueued on the HIP stream given at creation (or by
+ *    gbr_set_stream); calls return without waiting unless stated.
+ *  - Batch-first: calls take an array of n >= 0 grid handles and per-grid
+ *    pointer arrays; n = 0 is a no-op that returns GBR_OK.
+ *  - No exception or abort crosses the ABI. On error the status is returned
+ *    and gbr_last_error(g) describes it until the next call on g. One host
+ *    thread may use a handle at a time.
+ */
+#ifndef GBR_H
+#define GBR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gbr_status {
+    GBR_OK = 0,
+    GBR_E_ARG = 1,         /* invalid argument (null pointer, bad size or mode)    */
+    GBR_E_JACOBIAN = 2,    /* a cell has 1/J <= 0 (folded or left-handed grid)     */
+    GBR_E_STATE = 3,       /* non-physical state: rho <= 0, p <= 0 or non-finite   */
+    GBR_E_NOMEM = 4,       /* device allocation failed                             */
+    GBR_E_DEVICE = 5,      /* HIP runtime error                                    */
+    GBR_E_UNSUPPORTED = 6  /* option not implemented                              */
+} gbr_status;
+
+enum { GBR_LIM_NONE = 0, GBR_LIM_MP = 1, GBR_LIM_DUCROS = 2 };
+enum { GBR_FP64 = 0 };
+enum { GBR_DT_CFL = 0, GBR_DT_FIXED = 1 };
+
+typedef struct gbr_config {
+    int32_t ndim;      /* 2 or 3 (n[2] must be 1 when ndim == 2)                  */
+    int32_t n[3];      /* cells along xi, eta, zeta; each >= 1                    */
+    int32_t viscous;   /* 0 Euler, 1 Navier-Stokes with alpha-damping (Sec. 5.2)  */
+    int32_t limiter;   /* GBR_LIM_*: none, MP limiter on every interface (the     */
+                       /* paper, App. E), or MP where a Ducros sensor flags       */
+    int32_t moving;    /* 1: grid velocities are supplied, GCL terms (Sec. 4.2)   */
+    int32_t precision; /* GBR_FP64                                                */
+    double off[3][3];  /* periodic coordinate shift per wrapped direction         */
+    double gamma;      /* ratio of specific heats (1.4 in the paper)              */
+    double Pr;         /* Prandtl number (0.71)                                   */
+    double Re;         /* Reynolds number: mu = Sutherland(T) / Re                */
+    double Mref;       /* reference Mach number: p = rho T / (gamma Mref^2)       */
+    double suth;       /* Sutherland constant over the reference temperature     */
+    double theta_c;    /* shock-sensor threshold (GBR_LIM_DUCROS)                 */
+    double alpha_mp;   /* MP limiter alpha (4)                                    */
+    double beta_mp;    /* MP limiter beta (4)                                     */
+    double alpha_d;    /* alpha-damping coefficient alpha^D (4, Sec. 5.2)         */
+} gbr_config;
+
+typedef struct gbr_grid_s *gbr_grid;
+
+/* Metric inspection slots for gbr_metric_ptr. A face slot value stored at
+ * cell (i, j, k) belongs to the interface between that cell and its +1
+ * neighbour along the family direction f.                                   */
+#define GBR_SLOT_FACE_HAT(f, c)      ((f) * 13 + (c))                 /* hat f_c      */
+#define GBR_SLOT_FACE_HATT(f)        ((f) * 13 + 3)                   /* hat f_t      */
+#define GBR_SLOT_FACE_UNHAT(f, e, c) ((f) * 13 + 4 + (e) * 3 + (c))   /* e_c at face f */
+#define GBR_SLOT_CELL_UNHAT(e, c)    (39 + (e) * 3 + (c))             /* e_c          */
+#define GBR_SLOT_CELL_J              48                               /* J            */
+#define GBR_SLOT_CELL_INVJ           49                               /* 1/J          */
+#define GBR_SLOT_CELL_INVJT          50                               /* (1/J)_t      */
+#define GBR_SLOT_CELL_UNHATT(e)      (51 + (e))                       /* e_t          */
+#define GBR_SLOT_CELL_HAT(e, c)      (54 + (e) * 3 + (c))             /* hat e_c      */
+#define GBR_SLOT_CELL_HATT(e)        (63 + (e))                       /* hat e_t      */
+#define GBR_SLOT_COUNT               66
+
+/* Create a grid handle: validates cfg, allocates the library-owned device
+ * buffers (metrics, gradient and sensor scratch, RK and time-step storage;
+ * size given by gbr_grid_bytes) and binds hip_stream (a hipStream_t, or NULL
+ * for the default stream). Metrics are undefined until gbr_metrics.
+ * Errors: GBR_E_ARG (null pointer, ndim not 2/3, n < 1, n[2] != 1 in 2-D,
+ * unknown limiter or precision, non-positive gamma/Re/Pr/Mref),
+ * GBR_E_NOMEM, GBR_E_DEVICE. *out is NULL on error.                        */
+gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *out);
+
+/* Release a handle and its device buffers (waits for its stream). NULL is
+ * accepted.                                                                 */
+gbr_status gbr_grid_destroy(gbr_grid g);
+
+/* Device bytes gbr_grid_create allocates for cfg (0 if cfg is invalid): for
+ * admission against an HBM budget.                                          */
+size_t gbr_grid_bytes(const gbr_config *cfg);
+
+/* Rebind the stream used by later calls on g.                               */
+gbr_status gbr_set_stream(gbr_grid g, void *hip_stream);
+
+/* Metrics (Sec. 4.2, Sec. 7): conservative Thomas-Lombard metrics with the
+ * central derivative obtained from the inviscid interpolation (Eq. FP-interp,
+ * FP-interp2), the Jacobian (Eq. Jac-matrix), interface values of every
+ * metric with the same central formula (Eq. interp-formulae) and, if the grid
+ * is moving, the temporal metrics and (1/J)_t from the GCL (Eq. Jacb2).
+ * xyz[b]: cell-centre coordinates of grid b, [3][nk][nj][ni].
+ * xyz_t[b]: grid velocity at the cell centres, same layout; required (non
+ * NULL) for moving grids, ignored otherwise (xyz_t itself may be NULL).
+ * Synchronises the stream and returns GBR_E_JACOBIAN if any 1/J <= 0.       */
+gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz,
+                       const double *const *xyz_t);
+
+/* Right-hand side Res = d(Q/J)/dt (Sec. 3, Sec. 5.1 Steps 1-7, Sec. 5.2
+ * Steps 1-5): res[b] receives -sum_d [Phi(+1/2) - Phi(-1/2)] with
+ * Phi = F - F^v, the directions accumulated in the order xi, eta, zeta.
+ * Q[b]: conserved state (read only). res[b]: output, nvar arrays; must not
+ * alias Q[b]. Asynchronous; a non-physical state (cell or reconstructed
+ * interface) sets the grid's state flag, reported by gbr_check_state.      */
+gbr_status gbr_rhs(const gbr_grid *g, int n, const double *const *Q, void *const *res);
+
+/* One SSP-RK3 stage (App. B with Eq. time-split), in place on Q[b]:
+ *   Q <- a_s Qn + b_s (Q + dt J (Res - (1/J)_t Q)),
+ * (a_s, b_s) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 0, 1, 2.
+ * dt[b]: device pointer to the grid's time step (one double).             */
+gbr_status gbr_rk_stage(const gbr_grid *g, int n, int stage, const double *const *dt,
+                        const double *const *Qn, double *const *Q, const void *const *res);
+
+/* Time step (App. B): dt[b] <- cfl * min over cells and directions of
+ * 1/(|U| + c |grad d|), and for viscous grids also (1/alpha_d) min
+ * 1/(nu |grad d|^2). dt[b] is a device pointer; no host synchronisation.   */
+gbr_status gbr_cfl(const gbr_grid *g, int n, const double *const *Q, double cfl,
+                   double *const *dt);
+
+/* One SSP-RK3 step in place on Q[b]: for moving grids first the metrics at
+ * t^n from xyz[b], xyz_t[b] (Sec. 4.2: recomputed once per step), then the
+ * time step (dt_mode GBR_DT_CFL: cfl_or_dt is the CFL number; GBR_DT_FIXED:
+ * cfl_or_dt is dt), then three RHS evaluations and stages. Qn and Res are
+ * library-owned. dt_out[b] (device pointer, may be NULL / the array may be
+ * NULL) receives the step's dt. Asynchronous.                               */
+gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *const *xyz,
+                    const double *const *xyz_t, double cfl_or_dt, int dt_mode,
+                    double *const *dt_out);
+
+/* Synchronise g's stream and report flags raised since the last check:
+ * GBR_E_STATE (non-physical state) or GBR_E_JACOBIAN (from a gbr_step metric
+ * update). Clears the flags.                                                */
+gbr_status gbr_check_state(gbr_grid g);
+
+/* Read-only device pointer to one metric slot (GBR_SLOT_*), ncell doubles,
+ * owned by the library; NULL on a bad slot. Valid until gbr_grid_destroy.  */
+const double *gbr_metric_ptr(gbr_grid g, int slot);
+
+/* Message for the last error on g (static text for g == NULL). Valid until
+ * the next call on g.                                                       */
+const char *gbr_last_error(gbr_grid g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBR_H */

@@ -1,0 +1,60 @@
+// Internal declarations of the HIP implementation of gbr.h (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "gbr.h"
+
+// Library-owned state of one grid.
+struct gbr_grid_s {
+    gbr_config cfg;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    long ncell = 0;
+    int nvar = 0;
+    double *metrics = nullptr;   // GBR_SLOT_COUNT * ncell
+    double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
+    double *theta = nullptr;     // ncell: shock sensor
+    double *qn = nullptr;        // nvar * ncell: RK stage-0 state (gbr_step)
+    double *res = nullptr;       // nvar * ncell: RHS (gbr_step)
+    double *dt = nullptr;        // 1: time step of the last gbr_step / gbr_cfl
+    unsigned long long *dtmin = nullptr;  // 1: min-reduction word (bit pattern of a positive double)
+    int *flags = nullptr;        // [0] non-physical state, [1] non-positive Jacobian
+    std::string err;
+};
+
+namespace gbr {
+
+// Dimensions and physics parameters passed by value to kernels.
+struct Dims {
+    int n[3];
+    long ncell;
+};
+
+struct Phys {
+    double gamma;
+    double gm1;       // gamma - 1
+    double gM2;       // gamma Mref^2  (T = gM2 p / rho)
+    double suth;      // Sutherland S / T_ref
+    double inv_re;    // 1 / Re
+    double kfac;      // 1 / ((gamma - 1) Mref^2 Pr): kappa = mu * kfac
+    double theta_c;
+    double alpha_mp, beta_mp, alpha_d;
+    int limiter;
+};
+
+Dims dims_of(const gbr_grid_s *g);
+Phys phys_of(const gbr_grid_s *g);
+
+// Kernel launchers (enqueue on g->stream; return hipSuccess or the launch error).
+hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t);
+hipError_t launch_rhs(gbr_grid_s *g, const double *Q, double *res);
+hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
+                           double *Q, const double *res);
+hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
+hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
+hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);
+
+}  // namespace gbr

@@ -1,0 +1,201 @@
+// Metric kernels (Sec. 4.2, Sec. 7): conservative metrics, Jacobian,
+// interface values and GCL terms. FP64 throughout.
+//
+// Data flow (each a grid-wide kernel; one thread per cell):
+//   k_coord_deriv : D_d x_c of the periodic extension of the coordinates
+//                   (9 values per cell, into the scratch buffer)
+//   k_cell_metrics: hat(d)_c = D_d2[(c1)_d1 c2] - D_d1[(c1)_d2 c2] with the
+//                   products formed from the coordinates extended around the
+//                   cell, 1/J = det[D_d x_c], J, unhatted d_c = J hat(d)_c,
+//                   temporal metrics on moving grids
+//   k_face_metrics: interface values of the 3 hatted f-metrics, hat f_t and
+//                   all 9 unhatted metrics for each family f
+//   k_gcl         : (1/J)_t = -sum_f [I_f hat f_t](+1/2) - [...](-1/2)
+#include "gbr_device.hpp"
+#include "gbr_internal.hpp"
+
+namespace gbr {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct MetricArgs {
+    Dims dm;
+    int ndim;
+    double off[3][3];
+    const double *xyz;
+    const double *xyz_t;
+    double *dx;      // 9 * ncell
+    double *m;       // GBR_SLOT_COUNT * ncell
+    int *flags;
+};
+
+__device__ __forceinline__ void unpack(const Dims &dm, long idx, int ijk[3])
+{
+    ijk[0] = int(idx % dm.n[0]);
+    ijk[1] = int((idx / dm.n[0]) % dm.n[1]);
+    ijk[2] = int(idx / ((long)dm.n[0] * dm.n[1]));
+}
+
+__device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
+{
+    return i + (long)dm.n[0] * (j + (long)dm.n[1] * k);
+}
+
+// Linear index of the neighbour q steps along d, and how many periods it crossed.
+__device__ __forceinline__ long step_to(const Dims &dm, const int ijk[3], int d, int q, int *wraps)
+{
+    int t[3] = {ijk[0], ijk[1], ijk[2]};
+    int a = t[d] + q;
+    t[d] = wrap_index(a, dm.n[d]);
+    if (wraps) *wraps = wrap_count(a, dm.n[d]);
+    return pack(dm, t[0], t[1], t[2]);
+}
+
+// Coordinate c at linear index nb (z is the zeta index in 2-D).
+__device__ __forceinline__ double coord(const MetricArgs &a, int c, long nb)
+{
+    if (c == 2 && a.ndim == 2) return 0.0;
+    return a.xyz[c * a.dm.ncell + nb];
+}
+
+__global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    double v[11];
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) {
+            for (int q = -5; q <= 5; ++q) {
+                int wr;
+                long nb = step_to(a.dm, ijk, d, q, &wr);
+                v[q + 5] = coord(a, c, nb) + wr * a.off[d][c];
+            }
+            a.dx[(d * 3 + c) * a.dm.ncell + idx] = dcomp(v + 5);
+        }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    const long N = a.dm.ncell;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    double v[11];
+    double hat[3][3];
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            for (int q = -5; q <= 5; ++q) {
+                int wr;
+                long nb = step_to(a.dm, ijk, d2, q, &wr);
+                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * (coord(a, c2, nb) + wr * a.off[d2][c2]);
+            }
+            double ta = dcomp(v + 5);
+            for (int q = -5; q <= 5; ++q) {
+                int wr;
+                long nb = step_to(a.dm, ijk, d1, q, &wr);
+                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * (coord(a, c2, nb) + wr * a.off[d1][c2]);
+            }
+            hat[d][c] = ta - dcomp(v + 5);
+        }
+    }
+    double x[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) x[d][c] = a.dx[(d * 3 + c) * N + idx];
+    double invj = x[0][0] * (x[1][1] * x[2][2] - x[1][2] * x[2][1]) -
+                  x[0][1] * (x[1][0] * x[2][2] - x[1][2] * x[2][0]) +
+                  x[0][2] * (x[1][0] * x[2][1] - x[1][1] * x[2][0]);
+    if (!(invj > 0.0)) atomicOr(a.flags + 1, 1);
+    double jac = 1.0 / invj;
+    double *m = a.m;
+    m[GBR_SLOT_CELL_INVJ * N + idx] = invj;
+    m[GBR_SLOT_CELL_J * N + idx] = jac;
+    for (int d = 0; d < 3; ++d) {
+        for (int c = 0; c < 3; ++c) {
+            m[GBR_SLOT_CELL_HAT(d, c) * N + idx] = hat[d][c];
+            m[GBR_SLOT_CELL_UNHAT(d, c) * N + idx] = hat[d][c] / invj;
+        }
+        double ht = 0.0;
+        if (a.xyz_t) {
+            ht = -(a.xyz_t[idx] * hat[d][0] + a.xyz_t[N + idx] * hat[d][1] +
+                   (a.ndim == 3 ? a.xyz_t[2 * N + idx] * hat[d][2] : 0.0));
+        }
+        m[GBR_SLOT_CELL_HATT(d) * N + idx] = ht;
+        m[GBR_SLOT_CELL_UNHATT(d) * N + idx] = ht * jac;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    const long N = a.dm.ncell;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    long nb[10];
+    double v[10];
+    double *m = a.m;
+    for (int f = 0; f < 3; ++f) {
+        for (int q = -4; q <= 5; ++q) nb[q + 4] = step_to(a.dm, ijk, f, q, nullptr);
+        auto interp = [&](int slot) {
+            const double *s = m + slot * N;
+            for (int q = 0; q < 10; ++q) v[q] = s[nb[q]];
+            return face_interp(v + 4);
+        };
+        for (int c = 0; c < 3; ++c) m[GBR_SLOT_FACE_HAT(f, c) * N + idx] = interp(GBR_SLOT_CELL_HAT(f, c));
+        m[GBR_SLOT_FACE_HATT(f) * N + idx] = interp(GBR_SLOT_CELL_HATT(f));
+        for (int e = 0; e < 3; ++e)
+            for (int c = 0; c < 3; ++c)
+                m[GBR_SLOT_FACE_UNHAT(f, e, c) * N + idx] = interp(GBR_SLOT_CELL_UNHAT(e, c));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_gcl(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    const long N = a.dm.ncell;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    double s = 0.0;
+    for (int f = 0; f < 3; ++f) {
+        const double *ft = a.m + GBR_SLOT_FACE_HATT(f) * N;
+        s += ft[idx] - ft[step_to(a.dm, ijk, f, -1, nullptr)];
+    }
+    a.m[GBR_SLOT_CELL_INVJT * N + idx] = -s;
+}
+
+}  // namespace
+
+hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
+{
+    MetricArgs a;
+    a.dm = dims_of(g);
+    a.ndim = g->cfg.ndim;
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) a.off[d][c] = g->cfg.off[d][c];
+    if (a.ndim == 2) {
+        a.off[2][0] = 0.0;
+        a.off[2][1] = 0.0;
+        a.off[2][2] = 1.0;
+        for (int d = 0; d < 2; ++d) a.off[d][2] = 0.0;
+    }
+    a.xyz = xyz;
+    a.xyz_t = g->cfg.moving ? xyz_t : nullptr;
+    a.dx = g->scratch;
+    a.m = g->metrics;
+    a.flags = g->flags;
+    unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_coord_deriv, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    hipLaunchKernelGGL(k_cell_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    hipLaunchKernelGGL(k_face_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    hipLaunchKernelGGL(k_gcl, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace gbr
