@@ -1,0 +1,211 @@
+"""Benchmark: SSP-RK3 steps of the gradient-based-reconstruction solver on the
+13M-cell jet-shaped workload, one MI355X.
+
+A step is one full pass of the hot path: the CFL reduction, then three
+RHS evaluations (cell gradients and Ducros sensor, xi/eta/zeta interface
+sweeps with characteristic MP reconstruction, HLLC and alpha-damping
+viscous flux) each followed by an SSP-RK3 stage. Inputs (grid metrics and
+the state) are resident in HBM before timing starts.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints ONE JSON line on stdout (everything else goes to stderr).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NI, NJ, NK = 400, 180, 180
+PARAMS = dict(viscous=True, limiter="ducros", theta_c=0.5, Re=1.144e6, Mref=1.0)
+CFL = 0.2
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+PAPER_CONTEXT = {
+    "cell_rhs_per_s": 1.26e8,
+    "source": "derived from the paper's 34.5 h for 13M cells x 400,000 SSP-RK3 steps on one A100 "
+              "(FP64, MEG6 + alpha-damping, real jet with sponge/BCs); context, not this workload",
+}
+
+# Algorithmic (compulsory) HBM bytes per cell for each kernel class, 3-D
+# Navier-Stokes, FP64, static grid, Ducros sensor on: every input read once,
+# every output written once.
+ALG_BYTES_PER_CELL = {
+    "cell_grad": 40 + 72 + 96 + 8,        # Q, 9 cell metrics -> 12 gradients, theta
+    "sweep_xi": 40 + 96 + 64 + 8 + 8 + 40,   # Q, 12 face metrics, 8 tangential grads, T', theta, Res out
+    "sweep_eta": 40 + 96 + 64 + 8 + 8 + 80,  # ... Res in and out
+    "sweep_zeta": 40 + 96 + 64 + 8 + 8 + 80,
+    "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
+    "cfl": 40 + 72 + 24,                  # Q, 9 cell metrics, 3 temporal metrics
+    "copy": 80,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ("gbr_rhs.hip", "gbr_device.hpp", "gbr_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2303_10785_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or
+    None if absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_jet13m.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_digest") != source_digest():
+        return None
+    key = f"{kernel}_bytes_per_launch"
+    return float(vals[key]) if key in vals else None
+
+
+def cpu_baseline(grid, Q):
+    """The oracle as it stands, timed for one RHS evaluation on the full
+    workload (its metrics computed beforehand, not timed)."""
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"cpu baseline: oracle metrics on {NI}x{NJ}x{NK} ({threads} threads)")
+    m = oracle.metrics(grid, **PARAMS)
+    log("cpu baseline: timing one oracle RHS")
+    t0 = time.perf_counter()
+    oracle.rhs(grid, m, Q, **PARAMS)
+    t = time.perf_counter() - t0
+    ncell = NI * NJ * NK
+    return {"value": ncell / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one RHS evaluation of the full {NI}x{NJ}x{NK} jet workload "
+                      f"(NS, Ducros-gated MP, FP64), metrics precomputed; {t:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        log(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+            "(the build targets a single MI355X; multi-GPU sharding is a design note).")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2303_10785_amd import gbr
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"bench: generating {NI}x{NJ}x{NK} jet grid and state")
+    grid = W.jet3d((NI, NJ, NK))
+    Q0 = W.jet_ic(grid)
+    G = gbr.Grid(grid, **PARAMS)
+    xyz = torch.from_numpy(grid["xyz"]).to(dev)
+    G.metrics(xyz)
+    del xyz
+    Q = torch.from_numpy(Q0).to(dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    ncell = NI * NJ * NK
+
+    log(f"bench: {args.warmup} warmup steps")
+    for _ in range(args.warmup):
+        G.step(Q, CFL, gbr.GBR_DT_CFL, dt_out=dt)
+    torch.cuda.synchronize()
+    if G.check_state() != gbr.GBR_OK:
+        raise RuntimeError("non-physical state during warmup")
+
+    log(f"bench: timing {args.steps} steps")
+    gbr.gbr_timing_enable(G.h, True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        G.step(Q, CFL, gbr.GBR_DT_CFL, dt_out=dt)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    kern = gbr.gbr_timing_collect(G.h)
+    gbr.gbr_timing_enable(G.h, False)
+    state = G.check_state()
+    if state != gbr.GBR_OK:
+        raise RuntimeError(f"non-physical state in the timed steps ({state})")
+    ms_per_step = ms_total / args.steps
+    value = ncell * 3 * args.steps / (ms_total * 1e-3)
+    log(f"bench: {ms_per_step:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}), "
+        f"{value:.4e} cell-RHS/s, dt {dt.item():.4e}")
+
+    breakdown = {}
+    for k, (ms, cnt) in kern.items():
+        if cnt:
+            breakdown[k] = {"ms_per_launch": ms / cnt, "launches": cnt,
+                            "share": ms / ms_total}
+    dom = max((k for k in breakdown if k in ALG_BYTES_PER_CELL and k != "copy"),
+              key=lambda k: breakdown[k]["ms_per_launch"] * breakdown[k]["launches"])
+    alg = ALG_BYTES_PER_CELL[dom] * ncell
+    avg_s = breakdown[dom]["ms_per_launch"] * 1e-3
+    achieved = alg / avg_s / 1e9
+    traffic = read_traffic(dom)
+    for k, b in breakdown.items():
+        if k in ALG_BYTES_PER_CELL:
+            b["alg_GBps"] = ALG_BYTES_PER_CELL[k] * ncell / (b["ms_per_launch"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "alg_bytes_per_launch": alg}
+
+    line = {
+        "metric": "cell-updates/s per RHS at 13M cells (% HBM peak); batched solves/s + p99 latency",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded jet-shaped grid and tanh jet state with 1% velocity noise)",
+        "config": {"workload": f"jet-shaped stretched periodic curvilinear grid {NI}x{NJ}x{NK} "
+                               f"({ncell} cells), 3-D Navier-Stokes with alpha-damping, "
+                               f"Ducros-gated MP limiter, HLLC, SSP-RK3 at CFL {CFL}, FP64",
+                   "cells": ncell, "rhs_per_step": 3},
+        "roofline": roofline,
+        "kernels": breakdown,
+        "paper_context": PAPER_CONTEXT,
+    }
+    G.close()
+    del Q
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(grid, Q0)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,30 @@ gbr_status gbr_check_state(gbr_grid g);
  * owned by the library; NULL on a bad slot. Valid until gbr_grid_destroy.  */
 const double *gbr_metric_ptr(gbr_grid g, int slot);
 
+/* Kernel classes for gbr_timing_collect.                                   */
+enum {
+    GBR_K_METRICS = 0,     /* metric and GCL kernels                             */
+    GBR_K_CELL_GRAD = 1,   /* cell gradients and shock sensor                    */
+    GBR_K_SWEEP_XI = 2,    /* interface sweep along xi (writes Res)              */
+    GBR_K_SWEEP_ETA = 3,   /* interface sweep along eta                          */
+    GBR_K_SWEEP_ZETA = 4,  /* interface sweep along zeta                         */
+    GBR_K_RK_STAGE = 5,    /* SSP-RK3 stage update                               */
+    GBR_K_CFL = 6,         /* time-step reduction                                */
+    GBR_K_COPY = 7,        /* state copies and fills                             */
+    GBR_K_COUNT = 8
+};
+
+/* Per-kernel timing for benchmarks: while enabled (on != 0), every kernel
+ * launch on g is bracketed by two HIP events on g's stream. Disabling drops
+ * pending records.                                                          */
+gbr_status gbr_timing_enable(gbr_grid g, int on);
+
+/* Synchronise g's stream, add the duration of every recorded launch to
+ * ms[class] and count it in launches[class] (both arrays of GBR_K_COUNT
+ * entries, caller-owned host memory, accumulated into), and clear the
+ * records.                                                                  */
+gbr_status gbr_timing_collect(gbr_grid g, double *ms, long *launches);
+
 /* Message for the last error on g (static text for g == NULL). Valid until
  * the next call on g.                                                       */
 const char *gbr_last_error(gbr_grid g);

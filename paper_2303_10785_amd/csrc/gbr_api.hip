@@ -35,6 +35,37 @@ Phys phys_of(const gbr_grid_s *g)
     return p;
 }
 
+static hipEvent_t pooled_event(gbr_grid_s *g)
+{
+    if (!g->pool.empty()) {
+        hipEvent_t e = g->pool.back();
+        g->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+Timed::Timed(gbr_grid_s *g, int cls) : g_(g), cls_(cls)
+{
+    if (!g_->timing) return;
+    b_ = pooled_event(g_);
+    if (b_) (void)hipEventRecord(b_, g_->stream);
+}
+
+Timed::~Timed()
+{
+    if (!g_->timing || !b_) return;
+    hipEvent_t e = pooled_event(g_);
+    if (!e) {
+        g_->pool.push_back(b_);
+        return;
+    }
+    (void)hipEventRecord(e, g_->stream);
+    g_->recs.push_back({cls_, b_, e});
+}
+
 }  // namespace gbr
 
 namespace {
@@ -81,9 +112,21 @@ gbr_status hip_fail(gbr_grid_s *g, hipError_t e, const char *where)
     return e == hipErrorOutOfMemory ? GBR_E_NOMEM : GBR_E_DEVICE;
 }
 
+void drop_records(gbr_grid_s *g)
+{
+    for (auto &r : g->recs) {
+        g->pool.push_back(r.a);
+        g->pool.push_back(r.b);
+    }
+    g->recs.clear();
+}
+
 void release(gbr_grid_s *g)
 {
     if (!g) return;
+    drop_records(g);
+    for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
+    g->pool.clear();
     for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
@@ -289,6 +332,33 @@ const double *gbr_metric_ptr(gbr_grid g, int slot)
 {
     if (!g || slot < 0 || slot >= GBR_SLOT_COUNT) return nullptr;
     return g->metrics + (long)slot * g->ncell;
+}
+
+gbr_status gbr_timing_enable(gbr_grid g, int on)
+{
+    if (!g) return GBR_E_ARG;
+    if (!on) {
+        (void)hipStreamSynchronize(g->stream);
+        drop_records(g);
+    }
+    g->timing = on != 0;
+    return GBR_OK;
+}
+
+gbr_status gbr_timing_collect(gbr_grid g, double *ms, long *launches)
+{
+    if (!g || !ms || !launches) return GBR_E_ARG;
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "timing sync");
+    for (auto &r : g->recs) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.cls >= 0 && r.cls < GBR_K_COUNT) {
+            ms[r.cls] += t;
+            launches[r.cls] += 1;
+        }
+    }
+    drop_records(g);
+    return GBR_OK;
 }
 
 const char *gbr_last_error(gbr_grid g)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "gbr.h"
 
@@ -23,6 +24,11 @@ struct gbr_grid_s {
     unsigned long long *dtmin = nullptr;  // 1: min-reduction word (bit pattern of a positive double)
     int *flags = nullptr;        // [0] non-physical state, [1] non-positive Jacobian
     std::string err;
+    // kernel timing (gbr_timing_enable): event pairs per launch
+    bool timing = false;
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 };
 
 namespace gbr {
@@ -47,6 +53,21 @@ struct Phys {
 
 Dims dims_of(const gbr_grid_s *g);
 Phys phys_of(const gbr_grid_s *g);
+
+// Brackets the launches of one kernel class with timing events when the
+// grid's timing is enabled.
+class Timed {
+  public:
+    Timed(gbr_grid_s *g, int cls);
+    ~Timed();
+    Timed(const Timed &) = delete;
+    Timed &operator=(const Timed &) = delete;
+
+  private:
+    gbr_grid_s *g_;
+    int cls_;
+    hipEvent_t b_ = nullptr;
+};
 
 // Kernel launchers (enqueue on g->stream; return hipSuccess or the launch error).
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t);

@@ -191,6 +191,7 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
     a.m = g->metrics;
     a.flags = g->flags;
     unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_METRICS);
     hipLaunchKernelGGL(k_coord_deriv, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     hipLaunchKernelGGL(k_cell_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     hipLaunchKernelGGL(k_face_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);

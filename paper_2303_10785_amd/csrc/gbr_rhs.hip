@@ -483,9 +483,11 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
 }
 
 template <int D, int NDIM, bool VISC>
-hipError_t sweep(const RhsArgs &a, hipStream_t st)
+hipError_t sweep(gbr_grid_s *g, const RhsArgs &a)
 {
     using T = Tile<D>;
+    hipStream_t st = g->stream;
+    Timed timed(g, GBR_K_SWEEP_XI + D);
     const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
     const int tiles_s = (ns + T::TS - 2) / (T::TS - 1);
     const int tiles_c = (nc + T::TC - 1) / T::TC;
@@ -498,18 +500,22 @@ hipError_t sweep(const RhsArgs &a, hipStream_t st)
 }
 
 template <int NDIM, bool VISC>
-hipError_t rhs_all(const RhsArgs &a, hipStream_t st)
+hipError_t rhs_all(gbr_grid_s *g, const RhsArgs &a)
 {
     unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
-    if (a.ph.limiter == GBR_LIM_DUCROS)
-        hipLaunchKernelGGL((k_cell_grad<NDIM, true>), dim3(blocks), dim3(kBlock), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_cell_grad<NDIM, false>), dim3(blocks), dim3(kBlock), 0, st, a);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    {
+        Timed timed(g, GBR_K_CELL_GRAD);
+        if (a.ph.limiter == GBR_LIM_DUCROS)
+            hipLaunchKernelGGL((k_cell_grad<NDIM, true>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+        else
+            hipLaunchKernelGGL((k_cell_grad<NDIM, false>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
-    if ((e = sweep<0, NDIM, VISC>(a, st)) != hipSuccess) return e;
-    if ((e = sweep<1, NDIM, VISC>(a, st)) != hipSuccess) return e;
-    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC>(a, st);
+    if ((e = sweep<0, NDIM, VISC>(g, a)) != hipSuccess) return e;
+    if ((e = sweep<1, NDIM, VISC>(g, a)) != hipSuccess) return e;
+    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC>(g, a);
     return e;
 }
 
@@ -534,8 +540,8 @@ hipError_t launch_rhs(gbr_grid_s *g, const double *Q, double *res)
     RhsArgs a = make_args(g, Q, res);
     const bool visc = g->cfg.viscous != 0;
     if (g->cfg.ndim == 3)
-        return visc ? rhs_all<3, true>(a, g->stream) : rhs_all<3, false>(a, g->stream);
-    return visc ? rhs_all<2, true>(a, g->stream) : rhs_all<2, false>(a, g->stream);
+        return visc ? rhs_all<3, true>(g, a) : rhs_all<3, false>(g, a);
+    return visc ? rhs_all<2, true>(g, a) : rhs_all<2, false>(g, a);
 }
 
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
@@ -545,6 +551,7 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
     static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
     long n = (long)g->nvar * g->ncell;
     unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_RK_STAGE);
     hipLaunchKernelGGL(k_rk_stage, dim3(blocks), dim3(kBlock), 0, g->stream, n, g->ncell, A[stage],
                        B[stage], dt, Qn, Q, res, g->metrics + (long)GBR_SLOT_CELL_J * g->ncell,
                        g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell);
@@ -555,6 +562,7 @@ hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
 {
     RhsArgs a = make_args(g, Q, nullptr);
     unsigned blocks = unsigned((g->ncell + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_CFL);
     hipLaunchKernelGGL(k_set_word, dim3(1), dim3(1), 0, g->stream, g->dtmin, ~0ull >> 1);
     const bool visc = g->cfg.viscous != 0;
     if (g->cfg.ndim == 3) {
@@ -575,6 +583,7 @@ hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value)
 {
     unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_COPY);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kBlock), 0, g->stream, p, n, value);
     return hipGetLastError();
 }
@@ -582,6 +591,7 @@ hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value)
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n)
 {
     unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_COPY);
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, g->stream, dst, src, n);
     return hipGetLastError();
 }

@@ -114,10 +114,13 @@ def lib():
     L.gbr_check_state.argtypes = [_VP]
     L.gbr_metric_ptr.argtypes = [_VP, C.c_int]
     L.gbr_metric_ptr.restype = _VP
+    L.gbr_timing_enable.argtypes = [_VP, C.c_int]
+    L.gbr_timing_collect.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     L.gbr_last_error.argtypes = [_VP]
     L.gbr_last_error.restype = C.c_char_p
     for nm in ("gbr_grid_create", "gbr_grid_destroy", "gbr_set_stream", "gbr_metrics", "gbr_rhs",
-               "gbr_rk_stage", "gbr_cfl", "gbr_step", "gbr_check_state"):
+               "gbr_rk_stage", "gbr_cfl", "gbr_step", "gbr_check_state", "gbr_timing_enable",
+               "gbr_timing_collect"):
         getattr(L, nm).restype = C.c_int
     _lib = L
     return L
@@ -233,6 +236,22 @@ def gbr_check_state(h):
 
 def gbr_metric_ptr(h, slot):
     return lib().gbr_metric_ptr(h, int(slot))
+
+
+KERNEL_CLASSES = ["metrics", "cell_grad", "sweep_xi", "sweep_eta", "sweep_zeta", "rk_stage", "cfl", "copy"]
+
+
+def gbr_timing_enable(h, on=True):
+    _check(lib().gbr_timing_enable(h, int(bool(on))), h)
+
+
+def gbr_timing_collect(h):
+    """{class: (total ms, launches)} since the last collect."""
+    n = len(KERNEL_CLASSES)
+    ms = (C.c_double * n)()
+    cnt = (C.c_long * n)()
+    _check(lib().gbr_timing_collect(h, ms, cnt), h)
+    return {KERNEL_CLASSES[q]: (ms[q], cnt[q]) for q in range(n)}
 
 
 def gbr_last_error(h):
