@@ -38,10 +38,12 @@ PAPER_CONTEXT = {
 # Navier-Stokes, FP64, static grid, Ducros sensor on: every input read once,
 # every output written once.
 ALG_BYTES_PER_CELL = {
-    "cell_grad": 40 + 72 + 96 + 8,        # Q, 9 cell metrics -> 12 gradients, theta
-    "sweep_xi": 40 + 96 + 64 + 8 + 8 + 40,   # Q, 12 face metrics, 8 tangential grads, T', theta, Res out
-    "sweep_eta": 40 + 96 + 64 + 8 + 8 + 80,  # ... Res in and out
-    "sweep_zeta": 40 + 96 + 64 + 8 + 8 + 80,
+    "prims": 40 + 48,                     # Q -> rho, u, v, w, p, T
+    "cell_grad": 32 + 72 + 96 + 8,        # u, v, w, T, 9 cell metrics -> 12 gradients, theta
+    "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40,   # 5 primitives + T, 12 face metrics, 8 tangential
+                                             # grads, T', theta -> Res out
+    "sweep_eta": 48 + 96 + 64 + 8 + 8 + 80,  # ... Res in and out
+    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 80,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     "cfl": 40 + 72 + 24,                  # Q, 9 cell metrics, 3 temporal metrics
     "copy": 80,

@@ -170,7 +170,8 @@ enum {
     GBR_K_RK_STAGE = 5,    /* SSP-RK3 stage update                               */
     GBR_K_CFL = 6,         /* time-step reduction                                */
     GBR_K_COPY = 7,        /* state copies and fills                             */
-    GBR_K_COUNT = 8
+    GBR_K_PRIMS = 8,       /* primitive variables of the state                   */
+    GBR_K_COUNT = 9
 };
 
 /* Per-kernel timing for benchmarks: while enabled (on != 0), every kernel

@@ -24,6 +24,7 @@ Phys phys_of(const gbr_grid_s *g)
     p.gamma = c.gamma;
     p.gm1 = c.gamma - 1.0;
     p.gM2 = c.gamma * c.Mref * c.Mref;
+    p.inv_gm1 = 1.0 / (c.gamma - 1.0);
     p.suth = c.suth;
     p.inv_re = 1.0 / c.Re;
     p.kfac = 1.0 / ((c.gamma - 1.0) * c.Mref * c.Mref * c.Pr);
@@ -92,7 +93,7 @@ size_t bytes_for(const gbr_config *c)
 {
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     size_t nv = (size_t)c->ndim + 2;
-    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 2 * nv) + 1;
+    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 6 + 2 * nv) + 1 + gbr::kReducePartials;
     return doubles * sizeof(double) + sizeof(unsigned long long) + 2 * sizeof(int);
 }
 
@@ -127,7 +128,8 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->qn,
+    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->prim,
+                    (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
     delete g;
@@ -173,6 +175,8 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     alloc((void **)&g->metrics, N * GBR_SLOT_COUNT * sizeof(double));
     alloc((void **)&g->scratch, N * 12 * sizeof(double));
     alloc((void **)&g->theta, N * sizeof(double));
+    alloc((void **)&g->prim, N * 6 * sizeof(double));
+    alloc((void **)&g->partial, gbr::kReducePartials * sizeof(double));
     alloc((void **)&g->qn, N * g->nvar * sizeof(double));
     alloc((void **)&g->res, N * g->nvar * sizeof(double));
     alloc((void **)&g->dt, sizeof(double));

@@ -93,16 +93,18 @@ __device__ __forceinline__ double viscosity(double T, double suth, double inv_re
 // Curvilinear HLLC flux of Sec. 5.1.1 for primitive states L, R and
 // interface metrics (nt, nx, ny, nz) = (hat xi_t, hat xi_x, hat xi_y, hat xi_z).
 // One physical flux and at most one star state are formed: the selected side
-// K is L when S_L >= 0, R when S_R <= 0, else the side of S*.
+// K is L when S_L >= 0, R when S_R <= 0, else the side of S*. Reciprocals
+// are formed once and reused.
 __device__ __forceinline__ void hllc(const double PL[5], const double PR[5], double nt, double nx,
-                                     double ny, double nz, double gamma, double gm1, double F[5])
+                                     double ny, double nz, double gamma, double inv_gm1, double F[5])
 {
     double nn = nx * nx + ny * ny + nz * nz;
     double sn = sqrt(nn);
+    double irL = 1.0 / PL[0], irR = 1.0 / PR[0];
     double UL = nt + nx * PL[1] + ny * PL[2] + nz * PL[3];
     double UR = nt + nx * PR[1] + ny * PR[2] + nz * PR[3];
-    double cL = sqrt(gamma * PL[4] / PL[0]);
-    double cR = sqrt(gamma * PR[4] / PR[0]);
+    double cL = sqrt(gamma * PL[4] * irL);
+    double cR = sqrt(gamma * PR[4] * irR);
     double SL = fmin(UL - cL * sn, UR - cR * sn);
     double SR = fmax(UL + cL * sn, UR + cR * sn);
     double mL = PL[0] * (SL - UL), mR = PR[0] * (SR - UR);
@@ -111,26 +113,28 @@ __device__ __forceinline__ void hllc(const double PL[5], const double PR[5], dou
     bool useL = (0.0 <= SL) || (!(0.0 >= SR) && (0.0 <= Ss));
     bool star = !(0.0 <= SL) && !(0.0 >= SR);
     const double *P = useL ? PL : PR;
+    double ir = useL ? irL : irR;
     double U = useL ? UL : UR;
     double SK = useL ? SL : SR;
     double r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
-    double E = p / gm1 + 0.5 * r * (u * u + v * v + w * w);
+    double E = p * inv_gm1 + 0.5 * r * (u * u + v * v + w * w);
     F[0] = r * U;
     F[1] = r * u * U + nx * p;
     F[2] = r * v * U + ny * p;
     F[3] = r * w * U + nz * p;
     F[4] = (E + p) * U - nt * p;
     if (star) {
-        double fac = r * (SK - U) / (SK - Ss);
+        double sku = SK - U;
+        double fac = r * sku / (SK - Ss);
         double dS = Ss - U;
+        double inn = 1.0 / nn;
         // star momentum: u + n_a (S* - U) / |n|^2 (the printed components)
-        double g = dS / nn;
-        double q0 = fac;
+        double g = dS * inn;
         double q1 = fac * (u + nx * g);
         double q2 = fac * (v + ny * g);
         double q3 = fac * (w + nz * g);
-        double q4 = fac * (E / r + dS * ((Ss - nt) / nn + p / (r * (SK - U))));
-        F[0] += SK * (q0 - r);
+        double q4 = fac * (E * ir + dS * ((Ss - nt) * inn + p * ir / sku));
+        F[0] += SK * (fac - r);
         F[1] += SK * (q1 - r * u);
         F[2] += SK * (q2 - r * v);
         F[3] += SK * (q3 - r * w);

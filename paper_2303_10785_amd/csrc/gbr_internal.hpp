@@ -18,6 +18,8 @@ struct gbr_grid_s {
     double *metrics = nullptr;   // GBR_SLOT_COUNT * ncell
     double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
     double *theta = nullptr;     // ncell: shock sensor
+    double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
+    double *partial = nullptr;   // kReducePartials: per-block minima of the time-step reduction
     double *qn = nullptr;        // nvar * ncell: RK stage-0 state (gbr_step)
     double *res = nullptr;       // nvar * ncell: RHS (gbr_step)
     double *dt = nullptr;        // 1: time step of the last gbr_step / gbr_cfl
@@ -33,6 +35,8 @@ struct gbr_grid_s {
 
 namespace gbr {
 
+constexpr int kReducePartials = 4096;
+
 // Dimensions and physics parameters passed by value to kernels.
 struct Dims {
     int n[3];
@@ -43,6 +47,7 @@ struct Phys {
     double gamma;
     double gm1;       // gamma - 1
     double gM2;       // gamma Mref^2  (T = gM2 p / rho)
+    double inv_gm1;   // 1 / (gamma - 1)
     double suth;      // Sutherland S / T_ref
     double inv_re;    // 1 / Re
     double kfac;      // 1 / ((gamma - 1) Mref^2 Pr): kappa = mu * kfac

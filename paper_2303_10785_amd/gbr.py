@@ -238,7 +238,8 @@ def gbr_metric_ptr(h, slot):
     return lib().gbr_metric_ptr(h, int(slot))
 
 
-KERNEL_CLASSES = ["metrics", "cell_grad", "sweep_xi", "sweep_eta", "sweep_zeta", "rk_stage", "cfl", "copy"]
+KERNEL_CLASSES = ["metrics", "cell_grad", "sweep_xi", "sweep_eta", "sweep_zeta", "rk_stage", "cfl", "copy",
+                  "prims"]
 
 
 def gbr_timing_enable(h, on=True):
