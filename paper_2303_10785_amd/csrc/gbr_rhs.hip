@@ -9,15 +9,12 @@
 //                   zeta (kept for the tangential viscous terms) and the
 //                   Ducros sensor.
 //   k_sweep<D>    : per direction D, a tile of interfaces along D: primitive
-//                   pencils staged in LDS with a 6-cell halo, E6 first and
-//                   Hermite second derivatives formed once per cell in LDS.
-//                   Interfaces the limiter does not touch take the direct
-//                   van Leer states; the others are queued in LDS and
-//                   processed densely (characteristic projection, MP limiter,
-//                   back projection), so no wavefront idles on divergent
-//                   limiter work. Then every thread runs HLLC and the
-//                   alpha-damping viscous flux for its interface, the fluxes
-//                   go back to LDS and each cell accumulates
+//                   pencils staged in LDS with a 6-cell halo and E6 first
+//                   derivatives formed once per cell in LDS; one thread per
+//                   interface forms the Hermite second derivatives it needs,
+//                   the characteristic (limited) or direct van Leer states,
+//                   HLLC and the alpha-damping viscous flux. The fluxes go
+//                   back to LDS and each cell accumulates
 //                   -(Phi(+1/2) - Phi(-1/2)) into Res (written by the xi
 //                   sweep, updated by the others).
 // Tiles along D overlap by one interface, so no cell needs a flux computed by
@@ -75,58 +72,92 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs a)
         atomicOr(a.flags, 1);
 }
 
+// Gradient tile: GI x GJ cells in the (i, j) plane, marching KC planes along
+// k. Each k plane of (u, v, w, T) is staged in LDS with a 3-cell i/j halo for
+// the xi and eta derivatives; the zeta derivative comes from a 7-deep register
+// window along the thread's own column, so every value is read from HBM about
+// once.
+constexpr int GI = 32, GJ = kBlock / GI, KC = 16, HI = GI + 6, HJ = GJ + 6;
+
 template <int NDIM, bool SENSOR>
 __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs a)
 {
-    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
-    const long N = a.dm.ncell;
-    if (idx >= N) return;
-    int ijk[3];
-    ijk[0] = int(idx % a.dm.n[0]);
-    ijk[1] = int((idx / a.dm.n[0]) % a.dm.n[1]);
-    ijk[2] = int(idx / ((long)a.dm.n[0] * a.dm.n[1]));
-    const double *pu = a.prim + N;  // u, v, w at offsets 0, N, 2N; T at 4N
-    double gd[3][4];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (d >= NDIM) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) gd[d][s] = 0.0;
-            continue;
-        }
-        long nb[6];
+    __shared__ double sp[4][HJ][HI];
+    const Dims &dm = a.dm;
+    const long N = dm.ncell;
+    const int ni = dm.n[0], nj = dm.n[1], nk = dm.n[2];
+    const int tiles_i = (ni + GI - 1) / GI;
+    const int i0 = (blockIdx.x % tiles_i) * GI, j0 = (blockIdx.x / tiles_i) * GJ;
+    const int k0 = blockIdx.y * KC;
+    const int ti = threadIdx.x % GI, tj = threadIdx.x / GI;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool inside = i < ni && j < nj;
+    const int ic = min(i, ni - 1), jc = min(j, nj - 1);
+    const double *f[4] = {a.prim + N, a.prim + 2 * N, a.prim + 3 * N, a.prim + 5 * N};
+    double win[7][4];
+    if (NDIM == 3) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            int t[3] = {ijk[0], ijk[1], ijk[2]};
-            t[d] = wrap_index(t[d] + (q < 3 ? q - 3 : q - 2), a.dm.n[d]);
-            nb[q] = pack(a.dm, t[0], t[1], t[2]);
-        }
+            const long c = pack(dm, ic, jc, wrap_index(k0 - 3 + q, nk));
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const double *f = pu + (s < 3 ? s : 4) * N;
-            gd[d][s] = e6(f[nb[0]], f[nb[1]], f[nb[2]], f[nb[3]], f[nb[4]], f[nb[5]]);
+            for (int s = 0; s < 4; ++s) win[q][s] = f[s][c];
         }
     }
+    const int kend = min(k0 + KC, nk);
+    for (int k = k0; k < kend; ++k) {
+        if (NDIM == 3) {
+            const long c = pack(dm, ic, jc, wrap_index(k + 3, nk));
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+            for (int s = 0; s < 4; ++s) win[6][s] = f[s][c];
+        }
+        for (int e = threadIdx.x; e < HI * HJ; e += kBlock) {
+            const int x = e % HI, y = e / HI;
+            const long c = pack(dm, wrap_index(i0 - 3 + x, ni), wrap_index(j0 - 3 + y, nj), k);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
-    if (SENSOR) {
-        // physical velocity gradient G[a][b] = sum_d (d_{x_b}) du_a/dd
-        double G[3][3];
+            for (int s = 0; s < 4; ++s) sp[s][y][x] = f[s][c];
+        }
+        __syncthreads();
+        if (inside) {
+            const long idx = pack(dm, i, j, k);
+            double gd[3][4];
 #pragma unroll
-        for (int aa = 0; aa < 3; ++aa)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                double s = 0.0;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s += a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx] * gd[d][aa];
-                G[aa][b] = s;
+            for (int s = 0; s < 4; ++s) {
+                const double *r = &sp[s][tj + 3][ti + 3];
+                gd[0][s] = e6(r[-3], r[-2], r[-1], r[1], r[2], r[3]);
+                gd[1][s] = e6(r[-3 * HI], r[-2 * HI], r[-HI], r[HI], r[2 * HI], r[3 * HI]);
+                gd[2][s] = (NDIM == 3)
+                               ? e6(win[0][s], win[1][s], win[2][s], win[4][s], win[5][s], win[6][s])
+                               : 0.0;
             }
-        double div = G[0][0] + G[1][1] + G[2][2];
-        double wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
-        double d2 = div * div;
-        a.theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + 1e-30);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
+            if (SENSOR) {
+                // physical velocity gradient G[a][b] = sum_d (d_{x_b}) du_a/dd
+                double G[3][3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    double mb[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) mb[d] = a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx];
+#pragma unroll
+                    for (int aa = 0; aa < 3; ++aa)
+                        G[aa][b] = mb[0] * gd[0][aa] + mb[1] * gd[1][aa] + mb[2] * gd[2][aa];
+                }
+                double div = G[0][0] + G[1][1] + G[2][2];
+                double wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
+                double d2 = div * div;
+                a.theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + 1e-30);
+            }
+        }
+        __syncthreads();
+        if (NDIM == 3) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) win[q][s] = win[q + 1][s];
+        }
     }
 }
 
@@ -144,7 +175,6 @@ struct Tile {
     static constexpr int OD = (D == 2) ? 1 : 2;
     static constexpr int NP = TS + 11;  // primitive cells s0-6 .. s0+TS+4
     static constexpr int N1 = TS + 5;   // first derivatives s0-3 .. s0+TS+1
-    static constexpr int N2 = TS + 3;   // second derivatives s0-2 .. s0+TS
     static constexpr int ST = (D == 0) ? 1 : TC;  // LDS stride between cells along D
     // LDS offset of (s, c) in an array with ns entries along s: s fastest for
     // the xi sweep (lanes run along s), c fastest otherwise (lanes run along c).
@@ -163,15 +193,28 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
     return pack(dm, t[0], t[1], t[2]);
 }
 
+// Hermite second derivatives of the four cells a-1 .. a+2 of an interface
+// (Step-1 of Sec. 5.1) from the LDS primitives P (pointer at cell a) and
+// first derivatives G (pointer at cell a), one variable at stride st.
+template <int ST>
+__device__ __forceinline__ void second_derivs(const double *P, const double *G, double h[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int o = (q - 1) * ST;
+        h[q] = hermite2(P[o - ST], P[o], P[o + ST], G[o - ST], G[o + ST]);
+    }
+}
+
 // Limited interface states of Step-2..Step-5 of Sec. 5.1: characteristic
 // projection with the left eigenvectors of the averaged state and the unit
 // interface normal (App. A), unlimited van Leer states, MP limiter per
-// field (App. E), back projection. P, P1, P2 point at the LDS values of cell a
-// (the left cell) for primitives, first and second derivatives.
+// field (App. E), back projection. P, G point at the LDS primitives and first
+// derivatives of cell a (the left cell); vsP, vsG are the variable strides.
 template <int D>
-__device__ __forceinline__ void limited_states(const double *P, const double *P1, const double *P2,
-                                               int vsP, int vs1, int vs2, double nx, double ny,
-                                               double nz, const Phys &ph, double PL[5], double PR[5])
+__device__ __forceinline__ void limited_states(const double *P, const double *G, int vsP, int vsG,
+                                               double nx, double ny, double nz, const Phys &ph,
+                                               double PL[5], double PR[5])
 {
     constexpr int st = Tile<D>::ST;
     double rb = 0.5 * (P[0] + P[st]);
@@ -180,31 +223,39 @@ __device__ __forceinline__ void limited_states(const double *P, const double *P1
     double ra = rb * sqrt(ab2);
     double inn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
     double ex = nx * inn, ey = ny * inn, ez = nz * inn;
-    // projection of a primitive vector x (components at stride vs):
+    // projection of a primitive vector x:
     //   W0 = p - ra (e.u),  W4 = p + ra (e.u),
     //   (W1, W2, W3) = (ex s + (e x u)_x, ez s + (e x u)_z, -ey s - (e x u)_y),
     //   s = a^2 rho - p
-    auto project = [&](const double *x, int vs, double W[5]) {
-        double x0 = x[0], x1 = x[vs], x2 = x[2 * vs], x3 = x[3 * vs], x4 = x[4 * vs];
+    auto project = [&](double x0, double x1, double x2, double x3, double x4, double W[5]) {
         double un = ex * x1 + ey * x2 + ez * x3;
         double s = ab2 * x0 - x4;
-        double cx = ey * x3 - ez * x2;
-        double cy = ez * x1 - ex * x3;
-        double cz = ex * x2 - ey * x1;
         W[0] = x4 - ra * un;
-        W[1] = ex * s + cx;
-        W[2] = ez * s + cz;
-        W[3] = -ey * s - cy;
+        W[1] = ex * s + (ey * x3 - ez * x2);
+        W[2] = ez * s + (ex * x2 - ey * x1);
+        W[3] = -ey * s - (ez * x1 - ex * x3);
         W[4] = x4 + ra * un;
     };
+    // cell values W[q] (q = 0..3 -> cells a-1 .. a+2), curvatures W2[q],
+    // first derivatives W1[0..1] (cells a, a+1)
     double W[4][5], W2[4][5], W1[2][5];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        project(P + (q - 1) * st, vsP, W[q]);
-        project(P2 + (q - 1) * st, vs2, W2[q]);
+        const int o = (q - 1) * st;
+        project(P[o], P[vsP + o], P[2 * vsP + o], P[3 * vsP + o], P[4 * vsP + o], W[q]);
     }
-    project(P1, vs1, W1[0]);
-    project(P1 + st, vs1, W1[1]);
+    {
+        double h[5][4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) second_derivs<st>(P + v * vsP, G + v * vsG, h[v]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) project(h[0][q], h[1][q], h[2][q], h[3][q], h[4][q], W2[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = q * st;
+        project(G[o], G[vsG + o], G[2 * vsG + o], G[3 * vsG + o], G[4 * vsG + o], W1[q]);
+    }
     double WL[5], WR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -230,18 +281,18 @@ __device__ __forceinline__ void limited_states(const double *P, const double *P1
     back(WR, PR);
 }
 
+#ifndef GBR_SWEEP_WAVES_PER_EU
+#define GBR_SWEEP_WAVES_PER_EU 1
+#endif
+
 template <int D, int NDIM, bool VISC, bool FIRST>
-__global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
+__global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArgs a)
 {
     using T = Tile<D>;
-    constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, N2 = T::N2, st = T::ST;
-    constexpr int VP = NP * TC, V1 = N1 * TC, V2 = N2 * TC;
+    constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, st = T::ST;
+    constexpr int VP = NP * TC, V1 = N1 * TC;
     __shared__ double sP[5 * VP];
     __shared__ double s1[5 * V1];
-    __shared__ double s2[5 * V2];
-    __shared__ double sLR[10 * kBlock];
-    __shared__ int sList[kBlock];
-    __shared__ int sCount;
 
     const Dims &dm = a.dm;
     const Phys &ph = a.ph;
@@ -266,7 +317,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
 #pragma unroll
         for (int v = 0; v < 5; ++v) sP[v * VP + at] = a.prim[v * N + c];
     }
-    if (tid == 0) sCount = 0;
     __syncthreads();
     // Phase 2: E6 first derivatives of cells s0-3 .. s0+TS+1
     for (int e = tid; e < V1; e += kBlock) {
@@ -281,26 +331,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
         }
     }
     __syncthreads();
-    // Phase 3: Hermite second derivatives of cells s0-2 .. s0+TS
-    for (int e = tid; e < V2; e += kBlock) {
-        int sl = (D == 0) ? e % N2 : e / TC;
-        int cl = (D == 0) ? e / N2 : e % TC;
-        int pc = T::at(sl + 4, cl, NP);
-        int dc = T::at(sl + 1, cl, N1);
-        int at = T::at(sl, cl, N2);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const double *x = sP + v * VP + pc;
-            const double *g = s1 + v * V1 + dc;
-            s2[v * V2 + at] = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
-        }
-    }
-    __syncthreads();
 
-    // Phase 4a: one interface per thread, between cells s0+t-1 and s0+t.
-    // Unlimited interfaces take the direct van Leer states (Eq. vanleer-poly,
-    // identical to projecting and back-projecting since R R^-1 = I); limited
-    // ones are queued.
+    // Phase 3: one interface per thread, between cells a = s0+t-1 and a+1.
     const int t = T::t_of(tid);
     const int cl = T::c_of(tid);
     const int cg = c0 + cl;
@@ -308,45 +340,27 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
     const long ca = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t - 1, ns), cgc, o);
     const long cb = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t, ns), cgc, o);
     const double *Pa = sP + T::at(t + 5, cl, NP);
-    const double *P1a = s1 + T::at(t + 2, cl, N1);
-    const double *P2a = s2 + T::at(t + 2, cl, N2);  // cell a+1 (cell a is at -st)
+    const double *Ga = s1 + T::at(t + 2, cl, N1);
+    const double *m = a.m;
     bool limited = ph.limiter == GBR_LIM_MP;
     if (ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     double PL[5], PR[5];
-    if (!limited) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            PL[v] = Pa[v * VP] + 0.5 * P1a[v * V1] + kTwelfth * P2a[v * V2 - st];
-            PR[v] = Pa[v * VP + st] - 0.5 * P1a[v * V1 + st] + kTwelfth * P2a[v * V2];
-        }
-    } else {
-        sList[atomicAdd(&sCount, 1)] = tid;
-    }
-    __syncthreads();
-    // Phase 4b: the queued interfaces, one per thread, densely
-    const int nlim = sCount;
-    for (int k = tid; k < nlim; k += kBlock) {
-        const int f = sList[k];
-        const int tf = T::t_of(f), cf = T::c_of(f);
-        const long caf = cell_of(dm, T::SD, T::CD, wrap_index(s0 + tf - 1, ns), min(c0 + cf, nc - 1), o);
-        double nx = a.m[GBR_SLOT_FACE_HAT(D, 0) * N + caf];
-        double ny = a.m[GBR_SLOT_FACE_HAT(D, 1) * N + caf];
-        double nz = (NDIM == 3) ? a.m[GBR_SLOT_FACE_HAT(D, 2) * N + caf] : 0.0;
-        double L[5], R[5];
-        limited_states<D>(sP + T::at(tf + 5, cf, NP), s1 + T::at(tf + 2, cf, N1),
-                          s2 + T::at(tf + 1, cf, N2), VP, V1, V2, nx, ny, nz, ph, L, R);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            sLR[v * kBlock + f] = L[v];
-            sLR[(5 + v) * kBlock + f] = R[v];
-        }
-    }
-    __syncthreads();
     if (limited) {
+        double nx = m[GBR_SLOT_FACE_HAT(D, 0) * N + ca];
+        double ny = m[GBR_SLOT_FACE_HAT(D, 1) * N + ca];
+        double nz = (NDIM == 3) ? m[GBR_SLOT_FACE_HAT(D, 2) * N + ca] : 0.0;
+        limited_states<D>(Pa, Ga, VP, V1, nx, ny, nz, ph, PL, PR);
+    } else {
+        // Unlimited states of Eq. vanleer-poly directly in primitive form
+        // (identical to projecting and back-projecting since R R^-1 = I).
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            PL[v] = sLR[v * kBlock + tid];
-            PR[v] = sLR[(5 + v) * kBlock + tid];
+            const double *x = Pa + v * VP;
+            const double *g = Ga + v * V1;
+            double ha = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
+            double hb = hermite2(x[0], x[st], x[2 * st], g[0], g[2 * st]);
+            PL[v] = x[0] + 0.5 * g[0] + kTwelfth * ha;
+            PR[v] = x[st] - 0.5 * g[st] + kTwelfth * hb;
         }
     }
     if (NDIM == 2) {
@@ -355,8 +369,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
     }
     bool ok = PL[0] > 0.0 && PL[4] > 0.0 && PR[0] > 0.0 && PR[4] > 0.0;
 
-    // Phase 4c: HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2)
-    const double *m = a.m;
+    // HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2)
     const double nt = m[GBR_SLOT_FACE_HATT(D) * N + ca];
     const double nx = m[GBR_SLOT_FACE_HAT(D, 0) * N + ca];
     const double ny = m[GBR_SLOT_FACE_HAT(D, 1) * N + ca];
@@ -371,8 +384,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
         const double *Tc = a.prim + 5 * N;
         double c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], Tc[ca]};
         double c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], Tc[cb]};
-        double g0[4] = {P1a[V1], P1a[2 * V1], P1a[3 * V1], gr[(D * 4 + 3) * N + ca]};
-        double g1[4] = {P1a[V1 + st], P1a[2 * V1 + st], P1a[3 * V1 + st], gr[(D * 4 + 3) * N + cb]};
+        double g0[4] = {Ga[V1], Ga[2 * V1], Ga[3 * V1], gr[(D * 4 + 3) * N + ca]};
+        double g1[4] = {Ga[V1 + st], Ga[2 * V1 + st], Ga[3 * V1 + st], gr[(D * 4 + 3) * N + cb]};
         double sL[4], sR[4], gf[3][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -427,7 +440,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
 #pragma unroll
     for (int v = 0; v < 5; ++v) sP[v * kBlock + T::at(t, cl, TS)] = phi[v];
     __syncthreads();
-    // Phase 5: Res of cell s0+t from its two interfaces (Sec. 3, Step-7)
+    // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7)
     if (t < TS - 1 && s0 + t < ns && cg < nc) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -446,6 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs a)
 // ----------------------------------------------------------------------------
 // SSP-RK3 stage and time step
 // ----------------------------------------------------------------------------
+template <int NV>
 __global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, double cb,
                                                        const double *__restrict__ dtp,
                                                        const double *__restrict__ Qn,
@@ -456,11 +470,15 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, doub
 {
     long c = blockIdx.x * (long)kBlock + threadIdx.x;
     if (c >= ncell) return;
-    const long e = c + (long)blockIdx.y * ncell;
-    double dt = *dtp;
-    double q = Q[e];
-    double L = jac[c] * (res[e] - invjt[c] * q);
-    Q[e] = ca * Qn[e] + cb * (q + dt * L);
+    const double dt = *dtp;
+    const double J = jac[c], it = invjt[c];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const long e = c + v * ncell;
+        const double q = Q[e];
+        const double L = J * (res[e] - it * q);
+        Q[e] = ca * Qn[e] + cb * (q + dt * L);
+    }
 }
 
 // Per-block minimum of the admissible step over a grid-stride range of cells.
@@ -559,10 +577,12 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs &a)
     }
     {
         Timed timed(g, GBR_K_CELL_GRAD);
+        dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
+                unsigned((a.dm.n[2] + KC - 1) / KC));
         if (a.ph.limiter == GBR_LIM_DUCROS)
-            hipLaunchKernelGGL((k_cell_grad<NDIM, true>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+            hipLaunchKernelGGL((k_cell_grad<NDIM, true>), gg, dim3(kBlock), 0, g->stream, a);
         else
-            hipLaunchKernelGGL((k_cell_grad<NDIM, false>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+            hipLaunchKernelGGL((k_cell_grad<NDIM, false>), gg, dim3(kBlock), 0, g->stream, a);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -603,11 +623,16 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
 {
     static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
-    dim3 grid(unsigned((g->ncell + kBlock - 1) / kBlock), unsigned(g->nvar));
+    dim3 grid(unsigned((g->ncell + kBlock - 1) / kBlock));
+    const double *jac = g->metrics + (long)GBR_SLOT_CELL_J * g->ncell;
+    const double *ijt = g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell;
     Timed timed(g, GBR_K_RK_STAGE);
-    hipLaunchKernelGGL(k_rk_stage, grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage], dt,
-                       Qn, Q, res, g->metrics + (long)GBR_SLOT_CELL_J * g->ncell,
-                       g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell);
+    if (g->nvar == 5)
+        hipLaunchKernelGGL(k_rk_stage<5>, grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage],
+                           dt, Qn, Q, res, jac, ijt);
+    else
+        hipLaunchKernelGGL(k_rk_stage<4>, grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage],
+                           dt, Qn, Q, res, jac, ijt);
     return hipGetLastError();
 }
 
