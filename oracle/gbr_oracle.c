@@ -183,7 +183,13 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
     if (!dx) return -1;
     int bad = 0;
 
-    /* Step 1: coordinate derivatives D_d(x_c) at cell centres. */
+    /* The metrics are invariant under a translation of the coordinates (in
+     * the products below the shift multiplies D_d2 D_d1 - D_d1 D_d2 of a
+     * coordinate, which vanishes since the central derivatives commute), so
+     * every cell evaluates its windows with coordinates measured from its own
+     * centre. This only removes cancellation of O(|x| / dx) on grids far from
+     * the origin.
+     * Step 1: coordinate derivatives D_d(x_c) at cell centres. */
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; ++idx) {
         int ijk[3];
@@ -191,7 +197,7 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
         unpack(g, idx, ijk);
         for (int d = 0; d < 3; ++d)
             for (int c = 0; c < 3; ++c) {
-                for (int q = -5; q <= 5; ++q) w[q + 5] = coord_ext(g, xyz, ijk, d, q, c);
+                for (int q = -5; q <= 5; ++q) w[q + 5] = coord_ext(g, xyz, ijk, d, q, c) - xyz[c * N + idx];
                 dx[(d * 3 + c) * N + idx] = dcomp(w + 5);
             }
     }
@@ -209,13 +215,14 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
             int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
             for (int c = 0; c < 3; ++c) {
                 int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+                const double org = xyz[c2 * N + idx];
                 for (int q = -5; q <= 5; ++q)
                     w[q + 5] = dx[(d1 * 3 + c1) * N + neighbour(g, ijk, d2, q, NULL)]
-                               * coord_ext(g, xyz, ijk, d2, q, c2);
+                               * (coord_ext(g, xyz, ijk, d2, q, c2) - org);
                 double ta = dcomp(w + 5);
                 for (int q = -5; q <= 5; ++q)
                     w[q + 5] = dx[(d2 * 3 + c1) * N + neighbour(g, ijk, d1, q, NULL)]
-                               * coord_ext(g, xyz, ijk, d1, q, c2);
+                               * (coord_ext(g, xyz, ijk, d1, q, c2) - org);
                 double tb = dcomp(w + 5);
                 m[REF_M_HAT(d, c) * N + idx] = ta - tb;
             }
@@ -613,8 +620,8 @@ static int face_flux(const ref_cfg *g, const double *m, const double *Q, const d
         /* Step-3 and Step-4 per characteristic field. */
         double WL[5], WR[5];
         for (int s = 0; s < 5; ++s) {
-            double wl = W[1][s] + 0.5 * W1[0][s] + W2[1][s] / 12.0;
-            double wr = W[2][s] - 0.5 * W1[1][s] + W2[2][s] / 12.0;
+            double wl = W[1][s] + 0.5 * W1[0][s] + (1.0 / 12.0) * W2[1][s];
+            double wr = W[2][s] - 0.5 * W1[1][s] + (1.0 / 12.0) * W2[2][s];
             WL[s] = ref_mp_limit(W[0][s], W[1][s], W[2][s], W2[0][s], W2[1][s], W2[2][s],
                                  wl, g->alpha_mp, g->beta_mp);
             WR[s] = ref_mp_limit(W[3][s], W[2][s], W[1][s], W2[3][s], W2[2][s], W2[1][s],
@@ -627,8 +634,8 @@ static int face_flux(const ref_cfg *g, const double *m, const double *Q, const d
         /* Unlimited states of Eq. vanleer-poly directly in primitive form
          * (identical to projecting and back-projecting, as R R^-1 = I). */
         for (int s = 0; s < 5; ++s) {
-            PL[s] = PC(0)[s] + 0.5 * P1(0)[s] + P2(0)[s] / 12.0;
-            PR[s] = PC(1)[s] - 0.5 * P1(1)[s] + P2(1)[s] / 12.0;
+            PL[s] = PC(0)[s] + 0.5 * P1(0)[s] + (1.0 / 12.0) * P2(0)[s];
+            PR[s] = PC(1)[s] - 0.5 * P1(1)[s] + (1.0 / 12.0) * P2(1)[s];
         }
     }
     if (g->ndim == 2) { PL[3] = 0.0; PR[3] = 0.0; }
