@@ -48,7 +48,11 @@ typedef enum gbr_status {
 } gbr_status;
 
 enum { GBR_LIM_NONE = 0, GBR_LIM_MP = 1, GBR_LIM_DUCROS = 2 };
-enum { GBR_FP64 = 0 };
+/* Precision: GBR_FP64 computes everything in double. GBR_FP32_BULK keeps Q,
+ * the metrics, J, (1/J)_t, the time step and the RK accumulation in double
+ * and runs primitives, gradients, the sensor, reconstruction, limiter, HLLC,
+ * viscous flux and Res in float.                                            */
+enum { GBR_FP64 = 0, GBR_FP32_BULK = 1 };
 enum { GBR_DT_CFL = 0, GBR_DT_FIXED = 1 };
 
 typedef struct gbr_config {
@@ -58,7 +62,7 @@ typedef struct gbr_config {
     int32_t limiter;   /* GBR_LIM_*: none, MP limiter on every interface (the     */
                        /* paper, App. E), or MP where a Ducros sensor flags       */
     int32_t moving;    /* 1: grid velocities are supplied, GCL terms (Sec. 4.2)   */
-    int32_t precision; /* GBR_FP64                                                */
+    int32_t precision; /* GBR_FP64 or GBR_FP32_BULK                               */
     double off[3][3];  /* periodic coordinate shift per wrapped direction         */
     double gamma;      /* ratio of specific heats (1.4 in the paper)              */
     double Pr;         /* Prandtl number (0.71)                                   */
@@ -123,15 +127,16 @@ gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz,
 /* Right-hand side Res = d(Q/J)/dt (Sec. 3, Sec. 5.1 Steps 1-7, Sec. 5.2
  * Steps 1-5): res[b] receives -sum_d [Phi(+1/2) - Phi(-1/2)] with
  * Phi = F - F^v, the directions accumulated in the order xi, eta, zeta.
- * Q[b]: conserved state (read only). res[b]: output, nvar arrays; must not
- * alias Q[b]. Asynchronous; a non-physical state (cell or reconstructed
+ * Q[b]: conserved state (read only, double). res[b]: output, nvar arrays of
+ * double (GBR_FP64) or float (GBR_FP32_BULK); must not alias Q[b]. Asynchronous; a non-physical state (cell or reconstructed
  * interface) sets the grid's state flag, reported by gbr_check_state.      */
 gbr_status gbr_rhs(const gbr_grid *g, int n, const double *const *Q, void *const *res);
 
 /* One SSP-RK3 stage (App. B with Eq. time-split), in place on Q[b]:
  *   Q <- a_s Qn + b_s (Q + dt J (Res - (1/J)_t Q)),
  * (a_s, b_s) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 0, 1, 2.
- * dt[b]: device pointer to the grid's time step (one double).             */
+ * dt[b]: device pointer to the grid's time step (one double). res[b] has the
+ * grid's precision (double or float); the update itself is in double.      */
 gbr_status gbr_rk_stage(const gbr_grid *g, int n, int stage, const double *const *dt,
                         const double *const *Qn, double *const *Q, const void *const *res);
 

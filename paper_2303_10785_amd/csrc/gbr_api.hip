@@ -26,8 +26,8 @@ Phys phys_of(const gbr_grid_s *g)
     p.gM2 = c.gamma * c.Mref * c.Mref;
     p.inv_gm1 = 1.0 / (c.gamma - 1.0);
     p.suth = c.suth;
-    p.inv_re = 1.0 / c.Re;
-    p.kfac = 1.0 / ((c.gamma - 1.0) * c.Mref * c.Mref * c.Pr);
+    p.re = c.Re;
+    p.kden = (c.gamma - 1.0) * c.Mref * c.Mref * c.Pr;
     p.theta_c = c.theta_c;
     p.alpha_mp = c.alpha_mp;
     p.beta_mp = c.beta_mp;
@@ -83,7 +83,7 @@ bool config_ok(const gbr_config *c, const char **why)
     if ((long long)c->n[0] * c->n[1] * c->n[2] > (1ll << 31))
         return *why = "grid larger than 2^31 cells", false;
     if (c->limiter < GBR_LIM_NONE || c->limiter > GBR_LIM_DUCROS) return *why = "unknown limiter", false;
-    if (c->precision != GBR_FP64) return *why = "unsupported precision", false;
+    if (c->precision != GBR_FP64 && c->precision != GBR_FP32_BULK) return *why = "unsupported precision", false;
     if (!(c->gamma > 1.0) || !(c->Re > 0.0) || !(c->Pr > 0.0) || !(c->Mref > 0.0) || !(c->suth >= 0.0))
         return *why = "gamma must exceed 1 and Re, Pr, Mref be positive", false;
     return true;
@@ -244,7 +244,7 @@ gbr_status gbr_rhs(const gbr_grid *g, int n, const double *const *Q, void *const
     for (int b = 0; b < n; ++b) {
         if (!Q[b] || !res[b]) return fail(g[b], GBR_E_ARG, "null state or residual");
         if ((const void *)Q[b] == res[b]) return fail(g[b], GBR_E_ARG, "residual aliases the state");
-        hipError_t e = gbr::launch_rhs(g[b], Q[b], (double *)res[b]);
+        hipError_t e = gbr::launch_rhs(g[b], Q[b], res[b]);
         if (e != hipSuccess) return hip_fail(g[b], e, "rhs launch");
     }
     return GBR_OK;
@@ -260,7 +260,7 @@ gbr_status gbr_rk_stage(const gbr_grid *g, int n, int stage, const double *const
     if (!dt || !Qn || !Q || !res) return fail(g[0], GBR_E_ARG, "null pointer array");
     for (int b = 0; b < n; ++b) {
         if (!dt[b] || !Qn[b] || !Q[b] || !res[b]) return fail(g[b], GBR_E_ARG, "null pointer");
-        hipError_t e = gbr::launch_rk_stage(g[b], stage, dt[b], Qn[b], Q[b], (const double *)res[b]);
+        hipError_t e = gbr::launch_rk_stage(g[b], stage, dt[b], Qn[b], Q[b], res[b]);
         if (e != hipSuccess) return hip_fail(g[b], e, "rk stage launch");
     }
     return GBR_OK;

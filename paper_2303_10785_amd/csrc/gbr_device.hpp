@@ -45,22 +45,28 @@ __device__ __forceinline__ double face_interp(const double *v)
            w4 * (v[-3] + v[4]) + w5 * (v[-4] + v[5]);
 }
 
+// The RHS arithmetic below is templated on the compute type R: double for
+// the FP64 path, float for the FP32-bulk path.
+
 // E6 first derivative (Eq. E6_grads, as differences) from the six neighbours.
-__device__ __forceinline__ double e6(double m3, double m2, double m1, double p1, double p2, double p3)
+template <class R>
+__device__ __forceinline__ R e6(R m3, R m2, R m1, R p1, R p2, R p3)
 {
-    return 0.75 * (p1 - m1) - 0.15 * (p2 - m2) + (1.0 / 60.0) * (p3 - m3);
+    return R(0.75) * (p1 - m1) - R(0.15) * (p2 - m2) + R(1.0 / 60.0) * (p3 - m3);
 }
 
 // Hermite second derivative (Step-1 of Sec. 5.1).
-__device__ __forceinline__ double hermite2(double vm, double v0, double vp, double gm, double gp)
+template <class R>
+__device__ __forceinline__ R hermite2(R vm, R v0, R vp, R gm, R gp)
 {
-    return 2.0 * (vp - 2.0 * v0 + vm) - 0.5 * (gp - gm);
+    return R(2) * (vp - R(2) * v0 + vm) - R(0.5) * (gp - gm);
 }
 
-__device__ __forceinline__ double minmod(double a, double b)
+template <class R>
+__device__ __forceinline__ R minmod(R a, R b)
 {
     // 0.5 (sign a + sign b) min(|a|, |b|) with sign(0) = 0
-    double s = (a > 0.0 ? 0.5 : (a < 0.0 ? -0.5 : 0.0)) + (b > 0.0 ? 0.5 : (b < 0.0 ? -0.5 : 0.0));
+    R s = (a > R(0) ? R(0.5) : (a < R(0) ? R(-0.5) : R(0))) + (b > R(0) ? R(0.5) : (b < R(0) ? R(-0.5) : R(0)));
     return s * fmin(fabs(a), fabs(b));
 }
 
@@ -69,71 +75,66 @@ __device__ __forceinline__ double minmod(double a, double b)
 // downwind of the reconstructing cell, dm1, d0, dp1 their gradient-based
 // curvatures, wf the unlimited interface value. The right state is the same
 // procedure on the stencil reflected about its own cell.
-__device__ __forceinline__ double mp_limit(double wm1, double w0, double wp1, double dm1, double d0,
-                                           double dp1, double wf, double alpha, double beta)
+template <class R>
+__device__ __forceinline__ R mp_limit(R wm1, R w0, R wp1, R dm1, R d0, R dp1, R wf, R alpha, R beta)
 {
-    double wmp = w0 + minmod(wp1 - w0, beta * (w0 - wm1));
-    if ((wf - w0) * (wf - wmp) <= 1e-20) return wf;
-    double dmp = minmod(d0, dp1);
-    double dmm = minmod(dm1, d0);
-    double wmd = 0.5 * (w0 + wp1) - 0.5 * dmp;
-    double wul = w0 + alpha * (w0 - wm1);
-    double wlc = 0.5 * (3.0 * w0 - wm1) + (4.0 / 3.0) * dmm;
-    double lo = fmax(fmin(w0, fmin(wp1, wmd)), fmin(w0, fmin(wul, wlc)));
-    double hi = fmin(fmax(w0, fmax(wp1, wmd)), fmax(w0, fmax(wul, wlc)));
+    R wmp = w0 + minmod(wp1 - w0, beta * (w0 - wm1));
+    if ((wf - w0) * (wf - wmp) <= R(1e-20)) return wf;
+    R dmp = minmod(d0, dp1);
+    R dmm = minmod(dm1, d0);
+    R wmd = R(0.5) * (w0 + wp1) - R(0.5) * dmp;
+    R wul = w0 + alpha * (w0 - wm1);
+    R wlc = R(0.5) * (R(3) * w0 - wm1) + R(4.0 / 3.0) * dmm;
+    R lo = fmax(fmin(w0, fmin(wp1, wmd)), fmin(w0, fmin(wul, wlc)));
+    R hi = fmin(fmax(w0, fmax(wp1, wmd)), fmax(w0, fmax(wul, wlc)));
     return wf + minmod(lo - wf, hi - wf);
 }
 
 // Sutherland viscosity normalised to 1 at T = 1, divided by Re (Sec. 2).
-__device__ __forceinline__ double viscosity(double T, double suth, double inv_re)
+template <class R>
+__device__ __forceinline__ R viscosity(R T, R suth, R re)
 {
-    return T * sqrt(T) * (1.0 + suth) / (T + suth) * inv_re;
+    return T * sqrt(T) * (R(1) + suth) / (T + suth) / re;
 }
 
 // Curvilinear HLLC flux of Sec. 5.1.1 for primitive states L, R and
 // interface metrics (nt, nx, ny, nz) = (hat xi_t, hat xi_x, hat xi_y, hat xi_z).
 // One physical flux and at most one star state are formed: the selected side
-// K is L when S_L >= 0, R when S_R <= 0, else the side of S*. Reciprocals
-// are formed once and reused.
-__device__ __forceinline__ void hllc(const double PL[5], const double PR[5], double nt, double nx,
-                                     double ny, double nz, double gamma, double inv_gm1, double F[5])
+// K is L when S_L >= 0, R when S_R <= 0, else the side of S*. The wave speeds,
+// S* and the star state are evaluated in the order the paper prints them.
+template <class R>
+__device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R ny, R nz, R gamma,
+                                     R gm1, R F[5])
 {
-    double nn = nx * nx + ny * ny + nz * nz;
-    double sn = sqrt(nn);
-    double irL = 1.0 / PL[0], irR = 1.0 / PR[0];
-    double UL = nt + nx * PL[1] + ny * PL[2] + nz * PL[3];
-    double UR = nt + nx * PR[1] + ny * PR[2] + nz * PR[3];
-    double cL = sqrt(gamma * PL[4] * irL);
-    double cR = sqrt(gamma * PR[4] * irR);
-    double SL = fmin(UL - cL * sn, UR - cR * sn);
-    double SR = fmax(UL + cL * sn, UR + cR * sn);
-    double mL = PL[0] * (SL - UL), mR = PR[0] * (SR - UR);
-    double Ss = (mR * UR - mL * UL + (PL[4] - PR[4]) * nn) / (mR - mL);
+    R nn = nx * nx + ny * ny + nz * nz;
+    R sn = sqrt(nn);
+    R UL = nt + nx * PL[1] + ny * PL[2] + nz * PL[3];
+    R UR = nt + nx * PR[1] + ny * PR[2] + nz * PR[3];
+    R cL = sqrt(gamma * PL[4] / PL[0]);
+    R cR = sqrt(gamma * PR[4] / PR[0]);
+    R SL = fmin(UL - cL * sn, UR - cR * sn);
+    R SR = fmax(UL + cL * sn, UR + cR * sn);
+    R Ss = (PR[0] * UR * (SR - UR) - PL[0] * UL * (SL - UL) + (PL[4] - PR[4]) * nn) /
+           (PR[0] * (SR - UR) - PL[0] * (SL - UL));
 
-    bool useL = (0.0 <= SL) || (!(0.0 >= SR) && (0.0 <= Ss));
-    bool star = !(0.0 <= SL) && !(0.0 >= SR);
-    const double *P = useL ? PL : PR;
-    double ir = useL ? irL : irR;
-    double U = useL ? UL : UR;
-    double SK = useL ? SL : SR;
-    double r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
-    double E = p * inv_gm1 + 0.5 * r * (u * u + v * v + w * w);
+    bool useL = (R(0) <= SL) || (!(R(0) >= SR) && (R(0) <= Ss));
+    bool star = !(R(0) <= SL) && !(R(0) >= SR);
+    const R *P = useL ? PL : PR;
+    R U = useL ? UL : UR;
+    R SK = useL ? SL : SR;
+    R r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
+    R E = p / gm1 + R(0.5) * r * (u * u + v * v + w * w);
     F[0] = r * U;
     F[1] = r * u * U + nx * p;
     F[2] = r * v * U + ny * p;
     F[3] = r * w * U + nz * p;
     F[4] = (E + p) * U - nt * p;
     if (star) {
-        double sku = SK - U;
-        double fac = r * sku / (SK - Ss);
-        double dS = Ss - U;
-        double inn = 1.0 / nn;
-        // star momentum: u + n_a (S* - U) / |n|^2 (the printed components)
-        double g = dS * inn;
-        double q1 = fac * (u + nx * g);
-        double q2 = fac * (v + ny * g);
-        double q3 = fac * (w + nz * g);
-        double q4 = fac * (E * ir + dS * ((Ss - nt) * inn + p * ir / sku));
+        R fac = r * (SK - U) / (SK - Ss);
+        R q1 = fac * (nx * (Ss - nt) + (ny * ny + nz * nz) * u - ny * nx * v - nz * nx * w) / nn;
+        R q2 = fac * (ny * (Ss - nt) - nx * ny * u + (nx * nx + nz * nz) * v - nz * ny * w) / nn;
+        R q3 = fac * (nz * (Ss - nt) - nx * nz * u - ny * nz * v + (nx * nx + ny * ny) * w) / nn;
+        R q4 = fac * (E / r + (Ss - U) * ((Ss - nt) / nn + p / (r * (SK - U))));
         F[0] += SK * (fac - r);
         F[1] += SK * (q1 - r * u);
         F[2] += SK * (q2 - r * v);

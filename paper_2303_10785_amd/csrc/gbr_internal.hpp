@@ -21,7 +21,7 @@ struct gbr_grid_s {
     double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
     double *partial = nullptr;   // kReducePartials: per-block minima of the time-step reduction
     double *qn = nullptr;        // nvar * ncell: RK stage-0 state (gbr_step)
-    double *res = nullptr;       // nvar * ncell: RHS (gbr_step)
+    double *res = nullptr;       // nvar * ncell: RHS (gbr_step; float data in FP32-bulk)
     double *dt = nullptr;        // 1: time step of the last gbr_step / gbr_cfl
     unsigned long long *dtmin = nullptr;  // 1: min-reduction word (bit pattern of a positive double)
     int *flags = nullptr;        // [0] non-physical state, [1] non-positive Jacobian
@@ -49,8 +49,8 @@ struct Phys {
     double gM2;       // gamma Mref^2  (T = gM2 p / rho)
     double inv_gm1;   // 1 / (gamma - 1)
     double suth;      // Sutherland S / T_ref
-    double inv_re;    // 1 / Re
-    double kfac;      // 1 / ((gamma - 1) Mref^2 Pr): kappa = mu * kfac
+    double re;        // Re: mu = Sutherland(T) / Re
+    double kden;      // (gamma - 1) Mref^2 Pr: kappa = mu / kden
     double theta_c;
     double alpha_mp, beta_mp, alpha_d;
     int limiter;
@@ -76,9 +76,9 @@ class Timed {
 
 // Kernel launchers (enqueue on g->stream; return hipSuccess or the launch error).
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t);
-hipError_t launch_rhs(gbr_grid_s *g, const double *Q, double *res);
+hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res);
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
-                           double *Q, const double *res);
+                           double *Q, const void *res);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);

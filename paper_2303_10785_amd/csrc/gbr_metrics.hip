@@ -65,13 +65,16 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
     if (idx >= a.dm.ncell) return;
     int ijk[3];
     unpack(a.dm, idx, ijk);
+    // Coordinates are measured from the cell's own centre: the metrics are
+    // translation invariant and this avoids cancellation of O(|x| / dx).
     double v[11];
     for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 3; ++c) {
+            const double org = coord(a, c, idx);
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d, q, &wr);
-                v[q + 5] = coord(a, c, nb) + wr * a.off[d][c];
+                v[q + 5] = (coord(a, c, nb) - org) + wr * a.off[d][c];
             }
             a.dx[(d * 3 + c) * a.dm.ncell + idx] = dcomp(v + 5);
         }
@@ -90,16 +93,17 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a)
         const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3; ++c) {
             const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            const double org = coord(a, c2, idx);
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d2, q, &wr);
-                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * (coord(a, c2, nb) + wr * a.off[d2][c2]);
+                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) - org) + wr * a.off[d2][c2]);
             }
             double ta = dcomp(v + 5);
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d1, q, &wr);
-                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * (coord(a, c2, nb) + wr * a.off[d1][c2]);
+                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) - org) + wr * a.off[d1][c2]);
             }
             hat[d][c] = ta - dcomp(v + 5);
         }

@@ -7,7 +7,8 @@
 //                   and the positivity / finiteness check of the state.
 //   k_cell_grad   : per cell, E6 gradients of (u, v, w, T) along xi, eta,
 //                   zeta (kept for the tangential viscous terms) and the
-//                   Ducros sensor.
+//                   Ducros sensor; LDS-tiled in (i, j) with a register window
+//                   along k.
 //   k_sweep<D>    : per direction D, a tile of interfaces along D: primitive
 //                   pencils staged in LDS with a 6-cell halo and E6 first
 //                   derivatives formed once per cell in LDS; one thread per
@@ -19,6 +20,12 @@
 //                   sweep, updated by the others).
 // Tiles along D overlap by one interface, so no cell needs a flux computed by
 // another workgroup.
+//
+// Precision: the RHS kernels are templated on the compute type R. FP64 runs
+// everything in double. FP32-bulk (R = float) keeps primitives, gradients,
+// the sensor, the reconstruction, limiter, HLLC, viscous flux and Res in
+// float, while Q, the metrics, J and (1/J)_t stay in double and the RK stage
+// accumulates in double.
 #include "gbr_device.hpp"
 #include "gbr_internal.hpp"
 
@@ -26,17 +33,24 @@ namespace gbr {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr double kTwelfth = 1.0 / 12.0;
 
+template <class R>
+struct PhysR {
+    R gamma, gm1, gM2, suth, re, kden, theta_c, alpha_mp, beta_mp, alpha_d;
+    int limiter;
+};
+
+template <class R>
 struct RhsArgs {
     Dims dm;
-    Phys ph;
+    Phys ph;       // double parameters (time step, RK)
+    PhysR<R> pr;   // the same in the compute type
     const double *Q;
-    double *res;
-    double *grad;          // 12 * ncell: (d * 4 + s), s = u, v, w, T
-    double *theta;         // ncell
-    double *prim;          // 6 * ncell: rho, u, v, w, p, T
-    const double *m;       // metrics
+    R *res;
+    R *grad;       // 12 * ncell: (d * 4 + s), s = u, v, w, T
+    R *theta;      // ncell
+    R *prim;       // 6 * ncell: rho, u, v, w, p, T
+    const double *m;  // metrics (always double)
     int *flags;
 };
 
@@ -48,26 +62,25 @@ __device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
 // ----------------------------------------------------------------------------
 // primitives, cell gradients and sensor
 // ----------------------------------------------------------------------------
-template <int NDIM>
-__global__ void __launch_bounds__(kBlock) k_prims(RhsArgs a)
+template <int NDIM, class R>
+__global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     const long N = a.dm.ncell;
     if (idx >= N) return;
     double r = a.Q[idx];
-    double ir = 1.0 / r;
-    double u = a.Q[N + idx] * ir;
-    double v = a.Q[2 * N + idx] * ir;
-    double w = (NDIM == 3) ? a.Q[3 * N + idx] * ir : 0.0;
+    double u = a.Q[N + idx] / r;
+    double v = a.Q[2 * N + idx] / r;
+    double w = (NDIM == 3) ? a.Q[3 * N + idx] / r : 0.0;
     double E = a.Q[(NDIM + 1) * N + idx];
     double p = a.ph.gm1 * (E - 0.5 * r * (u * u + v * v + w * w));
-    double T = a.ph.gM2 * p * ir;
-    a.prim[idx] = r;
-    a.prim[N + idx] = u;
-    a.prim[2 * N + idx] = v;
-    a.prim[3 * N + idx] = w;
-    a.prim[4 * N + idx] = p;
-    a.prim[5 * N + idx] = T;
+    double T = a.ph.gM2 * p / r;
+    a.prim[idx] = R(r);
+    a.prim[N + idx] = R(u);
+    a.prim[2 * N + idx] = R(v);
+    a.prim[3 * N + idx] = R(w);
+    a.prim[4 * N + idx] = R(p);
+    a.prim[5 * N + idx] = R(T);
     if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)))
         atomicOr(a.flags, 1);
 }
@@ -79,10 +92,10 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs a)
 // once.
 constexpr int GI = 32, GJ = kBlock / GI, KC = 16, HI = GI + 6, HJ = GJ + 6;
 
-template <int NDIM, bool SENSOR>
-__global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs a)
+template <int NDIM, bool SENSOR, class R>
+__global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
 {
-    __shared__ double sp[4][HJ][HI];
+    __shared__ R sp[4][HJ][HI];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
     const int ni = dm.n[0], nj = dm.n[1], nk = dm.n[2];
@@ -93,8 +106,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs a)
     const int i = i0 + ti, j = j0 + tj;
     const bool inside = i < ni && j < nj;
     const int ic = min(i, ni - 1), jc = min(j, nj - 1);
-    const double *f[4] = {a.prim + N, a.prim + 2 * N, a.prim + 3 * N, a.prim + 5 * N};
-    double win[7][4];
+    const R *f[4] = {a.prim + N, a.prim + 2 * N, a.prim + 3 * N, a.prim + 5 * N};
+    R win[7][4];
     if (NDIM == 3) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -119,15 +132,14 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs a)
         __syncthreads();
         if (inside) {
             const long idx = pack(dm, i, j, k);
-            double gd[3][4];
+            R gd[3][4];
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const double *r = &sp[s][tj + 3][ti + 3];
+                const R *r = &sp[s][tj + 3][ti + 3];
                 gd[0][s] = e6(r[-3], r[-2], r[-1], r[1], r[2], r[3]);
                 gd[1][s] = e6(r[-3 * HI], r[-2 * HI], r[-HI], r[HI], r[2 * HI], r[3 * HI]);
-                gd[2][s] = (NDIM == 3)
-                               ? e6(win[0][s], win[1][s], win[2][s], win[4][s], win[5][s], win[6][s])
-                               : 0.0;
+                gd[2][s] = (NDIM == 3) ? e6(win[0][s], win[1][s], win[2][s], win[4][s], win[5][s], win[6][s])
+                                       : R(0);
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d)
@@ -135,20 +147,20 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs a)
                 for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
             if (SENSOR) {
                 // physical velocity gradient G[a][b] = sum_d (d_{x_b}) du_a/dd
-                double G[3][3];
+                R G[3][3];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    double mb[3];
+                    R mb[3];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) mb[d] = a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx];
+                    for (int d = 0; d < 3; ++d) mb[d] = R(a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx]);
 #pragma unroll
                     for (int aa = 0; aa < 3; ++aa)
                         G[aa][b] = mb[0] * gd[0][aa] + mb[1] * gd[1][aa] + mb[2] * gd[2][aa];
                 }
-                double div = G[0][0] + G[1][1] + G[2][2];
-                double wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
-                double d2 = div * div;
-                a.theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + 1e-30);
+                R div = G[0][0] + G[1][1] + G[2][2];
+                R wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
+                R d2 = div * div;
+                a.theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
             }
         }
         __syncthreads();
@@ -195,9 +207,9 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
 
 // Hermite second derivatives of the four cells a-1 .. a+2 of an interface
 // (Step-1 of Sec. 5.1) from the LDS primitives P (pointer at cell a) and
-// first derivatives G (pointer at cell a), one variable at stride st.
-template <int ST>
-__device__ __forceinline__ void second_derivs(const double *P, const double *G, double h[4])
+// first derivatives G (pointer at cell a), one variable at stride ST.
+template <int ST, class R>
+__device__ __forceinline__ void second_derivs(const R *P, const R *G, R h[4])
 {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -211,25 +223,25 @@ __device__ __forceinline__ void second_derivs(const double *P, const double *G, 
 // interface normal (App. A), unlimited van Leer states, MP limiter per
 // field (App. E), back projection. P, G point at the LDS primitives and first
 // derivatives of cell a (the left cell); vsP, vsG are the variable strides.
-template <int D>
-__device__ __forceinline__ void limited_states(const double *P, const double *G, int vsP, int vsG,
-                                               double nx, double ny, double nz, const Phys &ph,
-                                               double PL[5], double PR[5])
+template <int D, class R>
+__device__ __forceinline__ void limited_states(const R *P, const R *G, int vsP, int vsG, R nx, R ny, R nz,
+                                               const PhysR<R> &ph, R PL[5], R PR[5])
 {
     constexpr int st = Tile<D>::ST;
-    double rb = 0.5 * (P[0] + P[st]);
-    double pb = 0.5 * (P[4 * vsP] + P[4 * vsP + st]);
-    double ab2 = ph.gamma * pb / rb;
-    double ra = rb * sqrt(ab2);
-    double inn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
-    double ex = nx * inn, ey = ny * inn, ez = nz * inn;
+    const R twelfth = R(1.0 / 12.0);
+    R rb = R(0.5) * (P[0] + P[st]);
+    R pb = R(0.5) * (P[4 * vsP] + P[4 * vsP + st]);
+    R ab2 = ph.gamma * pb / rb;
+    R ra = rb * sqrt(ab2);
+    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
+    R ex = nx * inn, ey = ny * inn, ez = nz * inn;
     // projection of a primitive vector x:
     //   W0 = p - ra (e.u),  W4 = p + ra (e.u),
     //   (W1, W2, W3) = (ex s + (e x u)_x, ez s + (e x u)_z, -ey s - (e x u)_y),
     //   s = a^2 rho - p
-    auto project = [&](double x0, double x1, double x2, double x3, double x4, double W[5]) {
-        double un = ex * x1 + ey * x2 + ez * x3;
-        double s = ab2 * x0 - x4;
+    auto project = [&](R x0, R x1, R x2, R x3, R x4, R W[5]) {
+        R un = ex * x1 + ey * x2 + ez * x3;
+        R s = ab2 * x0 - x4;
         W[0] = x4 - ra * un;
         W[1] = ex * s + (ey * x3 - ez * x2);
         W[2] = ez * s + (ex * x2 - ey * x1);
@@ -238,14 +250,14 @@ __device__ __forceinline__ void limited_states(const double *P, const double *G,
     };
     // cell values W[q] (q = 0..3 -> cells a-1 .. a+2), curvatures W2[q],
     // first derivatives W1[0..1] (cells a, a+1)
-    double W[4][5], W2[4][5], W1[2][5];
+    R W[4][5], W2[4][5], W1[2][5];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int o = (q - 1) * st;
         project(P[o], P[vsP + o], P[2 * vsP + o], P[3 * vsP + o], P[4 * vsP + o], W[q]);
     }
     {
-        double h[5][4];
+        R h[5][4];
 #pragma unroll
         for (int v = 0; v < 5; ++v) second_derivs<st>(P + v * vsP, G + v * vsG, h[v]);
 #pragma unroll
@@ -256,46 +268,40 @@ __device__ __forceinline__ void limited_states(const double *P, const double *G,
         const int o = q * st;
         project(G[o], G[vsG + o], G[2 * vsG + o], G[3 * vsG + o], G[4 * vsG + o], W1[q]);
     }
-    double WL[5], WR[5];
+    R WL[5], WR[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        double wl = W[1][v] + 0.5 * W1[0][v] + kTwelfth * W2[1][v];
-        double wr = W[2][v] - 0.5 * W1[1][v] + kTwelfth * W2[2][v];
-        WL[v] = mp_limit(W[0][v], W[1][v], W[2][v], W2[0][v], W2[1][v], W2[2][v], wl, ph.alpha_mp,
-                         ph.beta_mp);
-        WR[v] = mp_limit(W[3][v], W[2][v], W[1][v], W2[3][v], W2[2][v], W2[1][v], wr, ph.alpha_mp,
-                         ph.beta_mp);
+        R wl = W[1][v] + R(0.5) * W1[0][v] + twelfth * W2[1][v];
+        R wr = W[2][v] - R(0.5) * W1[1][v] + twelfth * W2[2][v];
+        WL[v] = mp_limit(W[0][v], W[1][v], W[2][v], W2[0][v], W2[1][v], W2[2][v], wl, ph.alpha_mp, ph.beta_mp);
+        WR[v] = mp_limit(W[3][v], W[2][v], W[1][v], W2[3][v], W2[2][v], W2[1][v], wr, ph.alpha_mp, ph.beta_mp);
     }
     // right eigenvectors (App. A)
-    double ia2 = 1.0 / ab2;
-    double i2ra = 0.5 / ra;
-    auto back = [&](const double *w, double *x) {
-        double h = (w[4] - w[0]) * i2ra;
-        x[0] = (0.5 * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
+    R ia2 = R(1) / ab2;
+    R i2ra = R(0.5) / ra;
+    auto back = [&](const R *w, R *x) {
+        R h = (w[4] - w[0]) * i2ra;
+        x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
         x[1] = ex * h - ey * w[2] - ez * w[3];
         x[2] = ey * h - ez * w[1] + ex * w[2];
         x[3] = ez * h + ey * w[1] + ex * w[3];
-        x[4] = 0.5 * (w[0] + w[4]);
+        x[4] = R(0.5) * (w[0] + w[4]);
     };
     back(WL, PL);
     back(WR, PR);
 }
 
-#ifndef GBR_SWEEP_WAVES_PER_EU
-#define GBR_SWEEP_WAVES_PER_EU 1
-#endif
-
-template <int D, int NDIM, bool VISC, bool FIRST>
-__global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArgs a)
+template <int D, int NDIM, bool VISC, bool FIRST, class R>
+__global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
 {
     using T = Tile<D>;
     constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, st = T::ST;
     constexpr int VP = NP * TC, V1 = N1 * TC;
-    __shared__ double sP[5 * VP];
-    __shared__ double s1[5 * V1];
+    __shared__ R sP[5 * VP];
+    __shared__ R s1[5 * V1];
 
     const Dims &dm = a.dm;
-    const Phys &ph = a.ph;
+    const PhysR<R> &ph = a.pr;
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
     const int tiles_s = (ns + TS - 2) / (TS - 1);
@@ -305,6 +311,7 @@ __global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArg
     const int c0 = tcb * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
+    const R twelfth = R(1.0 / 12.0);
 
     // Phase 1: primitives of cells s0-6 .. s0+TS+4 into LDS
     for (int e = tid; e < VP; e += kBlock) {
@@ -326,7 +333,7 @@ __global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArg
         int at = T::at(sl, cl, N1);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double *x = sP + v * VP + pc;
+            const R *x = sP + v * VP + pc;
             s1[v * V1 + at] = e6(x[-3 * st], x[-2 * st], x[-st], x[st], x[2 * st], x[3 * st]);
         }
     }
@@ -339,94 +346,94 @@ __global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArg
     const int cgc = min(cg, nc - 1);
     const long ca = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t - 1, ns), cgc, o);
     const long cb = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t, ns), cgc, o);
-    const double *Pa = sP + T::at(t + 5, cl, NP);
-    const double *Ga = s1 + T::at(t + 2, cl, N1);
+    const R *Pa = sP + T::at(t + 5, cl, NP);
+    const R *Ga = s1 + T::at(t + 2, cl, N1);
     const double *m = a.m;
     bool limited = ph.limiter == GBR_LIM_MP;
     if (ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
-    double PL[5], PR[5];
+    R PL[5], PR[5];
     if (limited) {
-        double nx = m[GBR_SLOT_FACE_HAT(D, 0) * N + ca];
-        double ny = m[GBR_SLOT_FACE_HAT(D, 1) * N + ca];
-        double nz = (NDIM == 3) ? m[GBR_SLOT_FACE_HAT(D, 2) * N + ca] : 0.0;
+        R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
+        R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
+        R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
         limited_states<D>(Pa, Ga, VP, V1, nx, ny, nz, ph, PL, PR);
     } else {
         // Unlimited states of Eq. vanleer-poly directly in primitive form
         // (identical to projecting and back-projecting since R R^-1 = I).
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            const double *x = Pa + v * VP;
-            const double *g = Ga + v * V1;
-            double ha = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
-            double hb = hermite2(x[0], x[st], x[2 * st], g[0], g[2 * st]);
-            PL[v] = x[0] + 0.5 * g[0] + kTwelfth * ha;
-            PR[v] = x[st] - 0.5 * g[st] + kTwelfth * hb;
+            const R *x = Pa + v * VP;
+            const R *g = Ga + v * V1;
+            R ha = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
+            R hb = hermite2(x[0], x[st], x[2 * st], g[0], g[2 * st]);
+            PL[v] = x[0] + R(0.5) * g[0] + twelfth * ha;
+            PR[v] = x[st] - R(0.5) * g[st] + twelfth * hb;
         }
     }
     if (NDIM == 2) {
-        PL[3] = 0.0;
-        PR[3] = 0.0;
+        PL[3] = R(0);
+        PR[3] = R(0);
     }
-    bool ok = PL[0] > 0.0 && PL[4] > 0.0 && PR[0] > 0.0 && PR[4] > 0.0;
+    bool ok = PL[0] > R(0) && PL[4] > R(0) && PR[0] > R(0) && PR[4] > R(0);
 
     // HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2)
-    const double nt = m[GBR_SLOT_FACE_HATT(D) * N + ca];
-    const double nx = m[GBR_SLOT_FACE_HAT(D, 0) * N + ca];
-    const double ny = m[GBR_SLOT_FACE_HAT(D, 1) * N + ca];
-    const double nz = (NDIM == 3) ? m[GBR_SLOT_FACE_HAT(D, 2) * N + ca] : 0.0;
-    double phi[5];
-    hllc(PL, PR, nt, nx, ny, nz, ph.gamma, ph.inv_gm1, phi);
+    const R nt = R(m[GBR_SLOT_FACE_HATT(D) * N + ca]);
+    const R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
+    const R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
+    const R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
+    R phi[5];
+    hllc(PL, PR, nt, nx, ny, nz, ph.gamma, ph.gm1, phi);
     if (VISC) {
         // Step-1: interface gradients of (u, v, w, T) along each computational
         // direction; the normal one from Eq. AD-eqn1 (beta_D = 0), tangential
         // ones from the average of the two cell gradients.
-        const double *gr = a.grad;
-        const double *Tc = a.prim + 5 * N;
-        double c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], Tc[ca]};
-        double c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], Tc[cb]};
-        double g0[4] = {Ga[V1], Ga[2 * V1], Ga[3 * V1], gr[(D * 4 + 3) * N + ca]};
-        double g1[4] = {Ga[V1 + st], Ga[2 * V1 + st], Ga[3 * V1 + st], gr[(D * 4 + 3) * N + cb]};
-        double sL[4], sR[4], gf[3][4];
+        const R *gr = a.grad;
+        const R *Tc = a.prim + 5 * N;
+        R c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], Tc[ca]};
+        R c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], Tc[cb]};
+        R g0[4] = {Ga[V1], Ga[2 * V1], Ga[3 * V1], gr[(D * 4 + 3) * N + ca]};
+        R g1[4] = {Ga[V1 + st], Ga[2 * V1 + st], Ga[3 * V1 + st], gr[(D * 4 + 3) * N + cb]};
+        R sL[4], sR[4], gf[3][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            sL[s] = c0v[s] + 0.5 * g0[s];
-            sR[s] = c1v[s] - 0.5 * g1[s];
-            gf[D][s] = 0.5 * (g0[s] + g1[s]) + 0.5 * ph.alpha_d * (sR[s] - sL[s]);
+            sL[s] = c0v[s] + R(0.5) * g0[s];
+            sR[s] = c1v[s] - R(0.5) * g1[s];
+            gf[D][s] = R(0.5) * (g0[s] + g1[s]) + R(0.5) * ph.alpha_d * (sR[s] - sL[s]);
         }
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             if (e == D) continue;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                gf[e][s] = (e < NDIM) ? 0.5 * (gr[(e * 4 + s) * N + ca] + gr[(e * 4 + s) * N + cb]) : 0.0;
+                gf[e][s] = (e < NDIM) ? R(0.5) * (gr[(e * 4 + s) * N + ca] + gr[(e * 4 + s) * N + cb]) : R(0);
         }
         // Step-2: chain rule with the interface unhatted metrics
-        double Dx[4][3];
+        R Dx[4][3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            double mb[3];
+            R mb[3];
 #pragma unroll
             for (int e = 0; e < 3; ++e)
-                mb[e] = (e < NDIM && b < NDIM) ? m[GBR_SLOT_FACE_UNHAT(D, e, b) * N + ca] : 0.0;
+                mb[e] = (e < NDIM && b < NDIM) ? R(m[GBR_SLOT_FACE_UNHAT(D, e, b) * N + ca]) : R(0);
 #pragma unroll
             for (int s = 0; s < 4; ++s) Dx[s][b] = mb[0] * gf[0][s] + mb[1] * gf[1][s] + mb[2] * gf[2][s];
         }
         // Step-3: stresses and heat flux at the interface
-        double Tf = 0.5 * (sL[3] + sR[3]);
-        double mu = viscosity(Tf, ph.suth, ph.inv_re);
-        double lam = -2.0 / 3.0 * mu;
-        double kap = mu * ph.kfac;
-        double uf = 0.5 * (sL[0] + sR[0]), vf = 0.5 * (sL[1] + sR[1]), wf = 0.5 * (sL[2] + sR[2]);
-        double div = Dx[0][0] + Dx[1][1] + Dx[2][2];
-        double txx = 2.0 * mu * Dx[0][0] + lam * div;
-        double tyy = 2.0 * mu * Dx[1][1] + lam * div;
-        double tzz = 2.0 * mu * Dx[2][2] + lam * div;
-        double txy = mu * (Dx[0][1] + Dx[1][0]);
-        double txz = mu * (Dx[0][2] + Dx[2][0]);
-        double tyz = mu * (Dx[1][2] + Dx[2][1]);
-        double bx = uf * txx + vf * txy + wf * txz + kap * Dx[3][0];
-        double by = uf * txy + vf * tyy + wf * tyz + kap * Dx[3][1];
-        double bz = uf * txz + vf * tyz + wf * tzz + kap * Dx[3][2];
+        R Tf = R(0.5) * (sL[3] + sR[3]);
+        R mu = viscosity(Tf, ph.suth, ph.re);
+        R lam = R(-2.0 / 3.0) * mu;
+        R kap = mu / ph.kden;
+        R uf = R(0.5) * (sL[0] + sR[0]), vf = R(0.5) * (sL[1] + sR[1]), wf = R(0.5) * (sL[2] + sR[2]);
+        R div = Dx[0][0] + Dx[1][1] + Dx[2][2];
+        R txx = R(2) * mu * Dx[0][0] + lam * div;
+        R tyy = R(2) * mu * Dx[1][1] + lam * div;
+        R tzz = R(2) * mu * Dx[2][2] + lam * div;
+        R txy = mu * (Dx[0][1] + Dx[1][0]);
+        R txz = mu * (Dx[0][2] + Dx[2][0]);
+        R tyz = mu * (Dx[1][2] + Dx[2][1]);
+        R bx = uf * txx + vf * txy + wf * txz + kap * Dx[3][0];
+        R by = uf * txy + vf * tyy + wf * tyz + kap * Dx[3][1];
+        R bz = uf * txz + vf * tyz + wf * tzz + kap * Dx[3][2];
         // Step-4: viscous interface flux with the hatted interface metrics
         phi[1] -= nx * txx + ny * txy + nz * txz;
         phi[2] -= nx * txy + ny * tyy + nz * tyz;
@@ -446,8 +453,8 @@ __global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArg
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
             const int ov = (NDIM == 2 && v == 4) ? 3 : v;
-            const double d = sP[v * kBlock + T::at(t + 1, cl, TS)] - sP[v * kBlock + T::at(t, cl, TS)];
-            double *r = a.res + (long)ov * N + cb;
+            const R d = sP[v * kBlock + T::at(t + 1, cl, TS)] - sP[v * kBlock + T::at(t, cl, TS)];
+            R *r = a.res + (long)ov * N + cb;
             if (FIRST)
                 *r = -d;
             else
@@ -457,14 +464,14 @@ __global__ void __launch_bounds__(kBlock, GBR_SWEEP_WAVES_PER_EU) k_sweep(RhsArg
 }
 
 // ----------------------------------------------------------------------------
-// SSP-RK3 stage and time step
+// SSP-RK3 stage (double accumulation) and time step
 // ----------------------------------------------------------------------------
-template <int NV>
+template <int NV, class R>
 __global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, double cb,
                                                        const double *__restrict__ dtp,
                                                        const double *__restrict__ Qn,
                                                        double *__restrict__ Q,
-                                                       const double *__restrict__ res,
+                                                       const R *__restrict__ res,
                                                        const double *__restrict__ jac,
                                                        const double *__restrict__ invjt)
 {
@@ -476,37 +483,38 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, doub
     for (int v = 0; v < NV; ++v) {
         const long e = c + v * ncell;
         const double q = Q[e];
-        const double L = J * (res[e] - it * q);
+        const double L = J * (double(res[e]) - it * q);
         Q[e] = ca * Qn[e] + cb * (q + dt * L);
     }
 }
 
 // Per-block minimum of the admissible step over a grid-stride range of cells.
 template <int NDIM, bool VISC>
-__global__ void __launch_bounds__(kBlock) k_cfl_partial(RhsArgs a, double *partial)
+__global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const double *Q, const double *m,
+                                                          double *partial)
 {
-    const long N = a.dm.ncell;
+    const long N = dm.ncell;
     double best = __builtin_inf();
     for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
-        double r = a.Q[idx];
+        double r = Q[idx];
         double ir = 1.0 / r;
-        double u = a.Q[N + idx] * ir, v = a.Q[2 * N + idx] * ir;
-        double w = (NDIM == 3) ? a.Q[3 * N + idx] * ir : 0.0;
-        double p = a.ph.gm1 * (a.Q[(NDIM + 1) * N + idx] - 0.5 * r * (u * u + v * v + w * w));
-        double c = sqrt(a.ph.gamma * p * ir);
-        double nu = VISC ? viscosity(a.ph.gM2 * p * ir, a.ph.suth, a.ph.inv_re) * ir : 0.0;
+        double u = Q[N + idx] * ir, v = Q[2 * N + idx] * ir;
+        double w = (NDIM == 3) ? Q[3 * N + idx] * ir : 0.0;
+        double p = ph.gm1 * (Q[(NDIM + 1) * N + idx] - 0.5 * r * (u * u + v * v + w * w));
+        double c = sqrt(ph.gamma * p * ir);
+        double nu = VISC ? viscosity(ph.gM2 * p / r, ph.suth, ph.re) / r : 0.0;
         double bv = __builtin_inf();
 #pragma unroll
         for (int d = 0; d < NDIM; ++d) {
-            double dx = a.m[GBR_SLOT_CELL_UNHAT(d, 0) * N + idx];
-            double dy = a.m[GBR_SLOT_CELL_UNHAT(d, 1) * N + idx];
-            double dz = a.m[GBR_SLOT_CELL_UNHAT(d, 2) * N + idx];
-            double U = a.m[GBR_SLOT_CELL_UNHATT(d) * N + idx] + dx * u + dy * v + dz * w;
+            double dx = m[GBR_SLOT_CELL_UNHAT(d, 0) * N + idx];
+            double dy = m[GBR_SLOT_CELL_UNHAT(d, 1) * N + idx];
+            double dz = m[GBR_SLOT_CELL_UNHAT(d, 2) * N + idx];
+            double U = m[GBR_SLOT_CELL_UNHATT(d) * N + idx] + dx * u + dy * v + dz * w;
             double g2 = dx * dx + dy * dy + dz * dz;
             best = fmin(best, 1.0 / (fabs(U) + c * sqrt(g2)));
             if (VISC) bv = fmin(bv, 1.0 / (nu * g2));
         }
-        if (VISC) best = fmin(best, bv / a.ph.alpha_d);
+        if (VISC) best = fmin(best, bv / ph.alpha_d);
     }
     // wavefront minimum, then across the block's wavefronts
     for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
@@ -550,8 +558,8 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
     if (e < n) d[e] = s[e];
 }
 
-template <int D, int NDIM, bool VISC>
-hipError_t sweep(gbr_grid_s *g, const RhsArgs &a)
+template <int D, int NDIM, bool VISC, class R>
+hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a)
 {
     using T = Tile<D>;
     const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
@@ -560,66 +568,69 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs &a)
     dim3 grid(unsigned(tiles_s * tiles_c), unsigned(no));
     Timed timed(g, GBR_K_SWEEP_XI + D);
     if (D == 0)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, true>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, true, R>), grid, dim3(kBlock), 0, g->stream, a);
     else
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, false>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, false, R>), grid, dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }
 
-template <int NDIM, bool VISC>
-hipError_t rhs_all(gbr_grid_s *g, const RhsArgs &a)
+template <int NDIM, bool VISC, class R>
+hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a)
 {
     unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
     hipError_t e;
     {
         Timed timed(g, GBR_K_PRIMS);
-        hipLaunchKernelGGL((k_prims<NDIM>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_prims<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     }
     {
         Timed timed(g, GBR_K_CELL_GRAD);
         dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
                 unsigned((a.dm.n[2] + KC - 1) / KC));
-        if (a.ph.limiter == GBR_LIM_DUCROS)
-            hipLaunchKernelGGL((k_cell_grad<NDIM, true>), gg, dim3(kBlock), 0, g->stream, a);
+        if (a.pr.limiter == GBR_LIM_DUCROS)
+            hipLaunchKernelGGL((k_cell_grad<NDIM, true, R>), gg, dim3(kBlock), 0, g->stream, a);
         else
-            hipLaunchKernelGGL((k_cell_grad<NDIM, false>), gg, dim3(kBlock), 0, g->stream, a);
+            hipLaunchKernelGGL((k_cell_grad<NDIM, false, R>), gg, dim3(kBlock), 0, g->stream, a);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    if ((e = sweep<0, NDIM, VISC>(g, a)) != hipSuccess) return e;
-    if ((e = sweep<1, NDIM, VISC>(g, a)) != hipSuccess) return e;
-    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC>(g, a);
+    if ((e = sweep<0, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
+    if ((e = sweep<1, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
+    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R>(g, a);
     return e;
 }
 
-RhsArgs make_args(gbr_grid_s *g, const double *Q, double *res)
+template <class R>
+RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
 {
-    RhsArgs a;
+    RhsArgs<R> a;
     a.dm = dims_of(g);
     a.ph = phys_of(g);
+    const Phys &p = a.ph;
+    a.pr = PhysR<R>{R(p.gamma), R(p.gm1), R(p.gM2), R(p.suth), R(p.re), R(p.kden),
+                    R(p.theta_c), R(p.alpha_mp), R(p.beta_mp), R(p.alpha_d), p.limiter};
     a.Q = Q;
     a.res = res;
-    a.grad = g->scratch;
-    a.theta = g->theta;
-    a.prim = g->prim;
+    a.grad = reinterpret_cast<R *>(g->scratch);
+    a.theta = reinterpret_cast<R *>(g->theta);
+    a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;
     a.flags = g->flags;
     return a;
 }
 
-}  // namespace
-
-hipError_t launch_rhs(gbr_grid_s *g, const double *Q, double *res)
+template <class R>
+hipError_t rhs_typed(gbr_grid_s *g, const double *Q, R *res)
 {
-    RhsArgs a = make_args(g, Q, res);
+    RhsArgs<R> a = make_args<R>(g, Q, res);
     const bool visc = g->cfg.viscous != 0;
     if (g->cfg.ndim == 3)
-        return visc ? rhs_all<3, true>(g, a) : rhs_all<3, false>(g, a);
-    return visc ? rhs_all<2, true>(g, a) : rhs_all<2, false>(g, a);
+        return visc ? rhs_all<3, true, R>(g, a) : rhs_all<3, false, R>(g, a);
+    return visc ? rhs_all<2, true, R>(g, a) : rhs_all<2, false, R>(g, a);
 }
 
-hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
-                           const double *res)
+template <class R>
+hipError_t rk_typed(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q, const R *res)
 {
     static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
@@ -628,31 +639,52 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
     const double *ijt = g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell;
     Timed timed(g, GBR_K_RK_STAGE);
     if (g->nvar == 5)
-        hipLaunchKernelGGL(k_rk_stage<5>, grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage],
-                           dt, Qn, Q, res, jac, ijt);
+        hipLaunchKernelGGL((k_rk_stage<5, R>), grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage], dt,
+                           Qn, Q, res, jac, ijt);
     else
-        hipLaunchKernelGGL(k_rk_stage<4>, grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage],
-                           dt, Qn, Q, res, jac, ijt);
+        hipLaunchKernelGGL((k_rk_stage<4, R>), grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage], dt,
+                           Qn, Q, res, jac, ijt);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res)
+{
+    if (g->cfg.precision == GBR_FP32_BULK) return rhs_typed<float>(g, Q, static_cast<float *>(res));
+    return rhs_typed<double>(g, Q, static_cast<double *>(res));
+}
+
+hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
+                           const void *res)
+{
+    if (g->cfg.precision == GBR_FP32_BULK)
+        return rk_typed<float>(g, stage, dt, Qn, Q, static_cast<const float *>(res));
+    return rk_typed<double>(g, stage, dt, Qn, Q, static_cast<const double *>(res));
 }
 
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
 {
-    RhsArgs a = make_args(g, Q, nullptr);
+    const Dims dm = dims_of(g);
+    const Phys ph = phys_of(g);
     long want = (g->ncell + kBlock - 1) / kBlock;
     int blocks = int(want < kReducePartials ? want : kReducePartials);
     const bool visc = g->cfg.viscous != 0;
     Timed timed(g, GBR_K_CFL);
     if (g->cfg.ndim == 3) {
         if (visc)
-            hipLaunchKernelGGL((k_cfl_partial<3, true>), dim3(blocks), dim3(kBlock), 0, g->stream, a, g->partial);
+            hipLaunchKernelGGL((k_cfl_partial<3, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
+                               g->metrics, g->partial);
         else
-            hipLaunchKernelGGL((k_cfl_partial<3, false>), dim3(blocks), dim3(kBlock), 0, g->stream, a, g->partial);
+            hipLaunchKernelGGL((k_cfl_partial<3, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
+                               g->metrics, g->partial);
     } else {
         if (visc)
-            hipLaunchKernelGGL((k_cfl_partial<2, true>), dim3(blocks), dim3(kBlock), 0, g->stream, a, g->partial);
+            hipLaunchKernelGGL((k_cfl_partial<2, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
+                               g->metrics, g->partial);
         else
-            hipLaunchKernelGGL((k_cfl_partial<2, false>), dim3(blocks), dim3(kBlock), 0, g->stream, a, g->partial);
+            hipLaunchKernelGGL((k_cfl_partial<2, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
+                               g->metrics, g->partial);
     }
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, g->partial, blocks, cfl, dt);
     return hipGetLastError();

@@ -18,7 +18,8 @@ GBR_OK, GBR_E_ARG, GBR_E_JACOBIAN, GBR_E_STATE, GBR_E_NOMEM, GBR_E_DEVICE, GBR_E
 STATUS_NAMES = {0: "GBR_OK", 1: "GBR_E_ARG", 2: "GBR_E_JACOBIAN", 3: "GBR_E_STATE",
                 4: "GBR_E_NOMEM", 5: "GBR_E_DEVICE", 6: "GBR_E_UNSUPPORTED"}
 LIM = {"none": 0, "mp": 1, "ducros": 2}
-GBR_FP64 = 0
+GBR_FP64, GBR_FP32_BULK = 0, 1
+PRECISION = {"fp64": GBR_FP64, "fp32_bulk": GBR_FP32_BULK}
 GBR_DT_CFL, GBR_DT_FIXED = 0, 1
 
 
@@ -161,7 +162,7 @@ def _check(status, handle=None):
 
 def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1.4, Pr=0.71,
                 Re=1e4, Mref=1.0, suth=110.4 / 293.0, theta_c=0.5, alpha_mp=4.0, beta_mp=4.0,
-                alpha_d=4.0):
+                alpha_d=4.0, precision="fp64"):
     c = gbr_config()
     c.ndim = int(ndim)
     for d in range(3):
@@ -169,7 +170,7 @@ def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1
     c.viscous = int(bool(viscous))
     c.limiter = LIM[limiter] if isinstance(limiter, str) else int(limiter)
     c.moving = int(bool(moving))
-    c.precision = GBR_FP64
+    c.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     flat = [float(v) for row in off for v in row]
     for q in range(9):
         c.off[q] = flat[q]
@@ -273,6 +274,7 @@ class Grid:
         self.nvar = self.ndim + 2
         self.moving = grid.get("xyz_t") is not None or params.pop("moving", False)
         self.cfg = make_config(self.n, self.ndim, grid["off"], moving=self.moving, **params)
+        self.precision = self.cfg.precision
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.h = gbr_grid_create(self.cfg)
 
@@ -306,6 +308,10 @@ class Grid:
     def step(self, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None):
         gbr_step([self.h], [Q], cfl_or_dt, dt_mode, [xyz] if xyz is not None else None,
                  [xyz_t] if xyz_t is not None else None, [dt_out] if dt_out is not None else None)
+
+    def res_dtype(self):
+        import torch
+        return torch.float32 if self.precision == GBR_FP32_BULK else torch.float64
 
     def check_state(self):
         return gbr_check_state(self.h)

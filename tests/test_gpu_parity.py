@@ -276,3 +276,83 @@ def test_argument_errors(gbr):
     assert ei.value.status == gbr.GBR_E_ARG
     h.close()
     mv.close()
+
+
+# ---------------------------------------------------------------------------
+# FP32-bulk: reconstruction, limiter, HLLC and viscous flux in float; Q,
+# metrics, J, (1/J)_t and the RK accumulation in double. Compared with the
+# FP64 oracle under the stated bounds.
+# ---------------------------------------------------------------------------
+FP32_RHS_TOL = 2e-4     # per-variable max relative error of one RHS
+FP32_STEP_TOL = 1e-5    # per-variable max relative error of Q after 10 steps
+
+FP32_CASES = [
+    ("c1_vortex_euler_mp", "wavy2d_64", lambda g: W.shu_vortex(g, eps=5.0, xc=5.0, yc=5.0),
+     dict(limiter="mp")),
+    ("3d_smooth_ns_mp", "random3d_21x13x9", lambda g: W.random_smooth_state(g, seed=5),
+     dict(viscous=True, limiter="mp", Re=100.0, Mref=0.5)),
+    ("3d_moving_ns_mp", "deforming3d_16", lambda g: W.random_smooth_state(g, seed=6),
+     dict(viscous=True, limiter="mp", Re=1e4, Mref=0.5)),
+    ("jet_ns_ducros", "jet3d_48x20x18", lambda g: W.jet_ic(g),
+     dict(viscous=True, limiter="ducros", Re=1.144e6)),
+]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=[c[0] for c in FP32_CASES])
+def test_fp32_bulk_rhs_within_bound(gbr, case):
+    name, gname, state, params = case
+    g = GRIDS[gname]()
+    Q = state(g)
+    say(f"[fp32 rhs] {name} n={g['n']}")
+    h = gbr.Grid(g, precision="fp32_bulk", **params)
+    h.metrics(dev(g["xyz"]), dev(g["xyz_t"]) if g["xyz_t"] is not None else None)
+    Qd = dev(Q)
+    res = torch.empty(Qd.shape, dtype=torch.float32, device="cuda")
+    h.rhs(Qd, res)
+    torch.cuda.synchronize()
+    assert h.check_state() == gbr.GBR_OK
+    h.close()
+    ref = oracle.rhs(g, oracle.metrics(g, **params), Q, **params)
+    e = rel(res.double().cpu().numpy(), ref)
+    say(f"[fp32 rhs] {name} max rel err vs FP64 oracle {e:.3e}")
+    assert e <= FP32_RHS_TOL
+
+
+def test_fp32_bulk_steps_config1(gbr):
+    g = GRIDS["wavy2d_64"]()
+    Q = W.shu_vortex(g, eps=5.0, xc=5.0, yc=5.0)
+    h = gbr.Grid(g, precision="fp32_bulk", limiter="mp")
+    h.metrics(dev(g["xyz"]))
+    m = oracle.metrics(g, limiter="mp")
+    Qd = dev(Q)
+    for _ in range(10):
+        h.step(Qd, 0.4, gbr.GBR_DT_CFL)
+        Q, _ = oracle.step(g, m, Q, 0.4, limiter="mp")
+    torch.cuda.synchronize()
+    e = rel(Qd.cpu().numpy(), Q)
+    say(f"[fp32 step] config1 10 steps max rel err {e:.3e}")
+    h.close()
+    assert e <= FP32_STEP_TOL
+
+
+def test_fp32_bulk_freestream_moving(gbr):
+    """FP32-bulk keeps freestream to single-precision round-off on a deforming
+    randomized grid (the metrics and GCL terms stay in double)."""
+    mv = W.Deforming3D((16, 16, 16), A=0.75, nmode=2, rand=0.2, seed=6)
+    g = mv.at(0.0)
+    pinf = 1.0 / (1.4 * 0.25)
+    Q = W.uniform_flow(g, 1.0, 1.0, 0.0, 0.0, pinf)
+    h = gbr.Grid(g, precision="fp32_bulk", viscous=True, limiter="mp", Mref=0.5, Re=1e4)
+    Qd = dev(Q)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = 0.0
+    for _ in range(10):
+        gt = mv.at(t)
+        h.step(Qd, 0.2, gbr.GBR_DT_CFL, xyz=dev(gt["xyz"]), xyz_t=dev(gt["xyz_t"]), dt_out=dt)
+        torch.cuda.synchronize()
+        t += dt.item()
+    rho, u, v, w, p = oracle.prim_from_Q(Qd.cpu().numpy())
+    vmax = max(np.abs(v).max(), np.abs(w).max())
+    say(f"[fp32 freestream] max |v|,|w| after 10 moving steps {vmax:.3e}")
+    h.close()
+    assert vmax < 1e-5
