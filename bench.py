@@ -140,12 +140,108 @@ def fp32_bulk_leg(G64, grid, Q0, args, dev, ncell):
             "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in kern.items() if v[1]}}
 
 
+BATCH_STEPS = 100
+BATCH_CFL = 0.4
+
+
+def batched_leg(dev):
+    """Many-small-grids workload: 256 periodic wavy 2-D Euler grids of
+    32^2..512^2 cells (vortex / Sod-vortex states), MP limiter, CFL 0.4 per
+    grid, 100 SSP-RK3 steps each. Timed as one batch (graph replay, tile
+    autotuned) in FP32-bulk and FP64, and as 256 separate FP64 solves through
+    gbr_step; the FP32-bulk results are compared per problem with the FP64
+    ones."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2303_10785_amd import gbr
+
+    t0 = time.perf_counter()
+    cases = W.batch2d()
+    cells = sum(g["n"][0] * g["n"][1] for g, _, _ in cases)
+    log(f"bench batched: {len(cases)} grids, {cells} cells, generated in {time.perf_counter() - t0:.1f}s")
+
+    def grids_for(precision):
+        hs = []
+        for g, _, _ in cases:
+            h = gbr.Grid(g, precision=precision, viscous=False, limiter="mp")
+            h.metrics(torch.from_numpy(g["xyz"]).to(dev))
+            hs.append(h)
+        return hs
+
+    def states():
+        return [torch.from_numpy(Q).to(dev) for _, Q, _ in cases]
+
+    def timed(fn):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        fn()
+        stop.record()
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) * 1e-3
+
+    out = {"workload": f"{len(cases)} periodic wavy 2-D Euler grids, N^2 cells with N = round(2^U(5,9)) "
+                       f"({cells} cells total), Shu vortex / Sod+vortex, MP limiter, "
+                       f"{BATCH_STEPS} SSP-RK3 steps each at CFL {BATCH_CFL}",
+           "grids": len(cases), "cells": cells, "steps_per_solve": BATCH_STEPS}
+    finals = {}
+    for precision in ("fp32_bulk", "fp64"):
+        hs = grids_for(precision)
+        Qs = states()
+        B = gbr.Batch(hs, Qs, tile=gbr.GBR_TILE_AUTO)
+        B.run(1, BATCH_CFL)  # captures the step graph
+        for q, (_, Q, _) in enumerate(cases):
+            Qs[q].copy_(torch.from_numpy(Q))
+        torch.cuda.synchronize()
+        sec = timed(lambda: B.run(BATCH_STEPS, BATCH_CFL))
+        _, _, tile = B.query()
+        ok = all(h.check_state() == gbr.GBR_OK for h in hs)
+        finals[precision] = [x.cpu().numpy() for x in Qs]
+        out[f"batched_{precision}"] = {
+            "seconds": sec, "solves_per_s": len(cases) / sec,
+            "cell_updates_per_s": cells * 3 * BATCH_STEPS / sec, "tile": gbr.TILE_NAMES[tile],
+            "state_ok": ok}
+        log(f"bench batched {precision}: {sec:.3f} s, {len(cases) / sec:.1f} solves/s, tile {gbr.TILE_NAMES[tile]}")
+        B.close()
+        if precision == "fp64":
+            # the same 256 problems solved one after another through gbr_step
+            Qs = states()
+            dt = torch.zeros(1, dtype=torch.float64, device=dev)
+
+            def per_solve():
+                for h, Q in zip(hs, Qs):
+                    for _ in range(BATCH_STEPS):
+                        h.step(Q, BATCH_CFL, gbr.GBR_DT_CFL, dt_out=dt)
+            sec1 = timed(per_solve)
+            ok1 = all(h.check_state() == gbr.GBR_OK for h in hs)
+            dev64 = max(float(np.abs(Q.cpu().numpy() - f).max() / max(np.abs(f).max(), 1e-300))
+                        for Q, f in zip(Qs, finals["fp64"]))
+            out["per_solve_fp64"] = {"seconds": sec1, "solves_per_s": len(cases) / sec1,
+                                     "cell_updates_per_s": cells * 3 * BATCH_STEPS / sec1,
+                                     "state_ok": ok1, "max_rel_diff_vs_batched_fp64": dev64}
+            log(f"bench per-solve fp64: {sec1:.3f} s, {len(cases) / sec1:.1f} solves/s")
+        for h in hs:
+            h.close()
+        del Qs
+        torch.cuda.empty_cache()
+    errs = []
+    for a, b in zip(finals["fp32_bulk"], finals["fp64"]):
+        errs.append(max(float(np.abs(a[v] - b[v]).max() / np.abs(b[v]).max()) for v in range(b.shape[0])))
+    out["fp32_vs_fp64_per_problem_max_rel_err"] = {"max": max(errs), "median": float(np.median(errs))}
+    out["speedup_batched_fp32_vs_per_solve_fp64"] = (out["batched_fp32_bulk"]["solves_per_s"]
+                                                     / out["per_solve_fp64"]["solves_per_s"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched many-grid leg")
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -247,6 +343,7 @@ def main():
     G.close()
     del Q
     torch.cuda.empty_cache()
+    line["batched"] = None if args.no_batch else batched_leg(dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(grid, Q0)
     else:

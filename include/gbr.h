@@ -190,6 +190,57 @@ gbr_status gbr_timing_enable(gbr_grid g, int on);
  * records.                                                                  */
 gbr_status gbr_timing_collect(gbr_grid g, double *ms, long *launches);
 
+/* ------------------------------------------------------------------------
+ * Batched stepping of many small 2-D Euler grids. One step of all grids is
+ * a handful of launches, each over every grid at once: a persistent kernel
+ * per SSP-RK3 stage walks a work list of (grid, tile) pairs and does all of
+ * Sec. 5.1 Steps 1-7 and the App. B stage update for its tile in LDS. The
+ * step can be captured once as a HIP graph and replayed.
+ * ---------------------------------------------------------------------- */
+typedef struct gbr_batch_s *gbr_batch;
+
+/* Tile shapes (cells along xi x eta) of the batched kernels.              */
+enum { GBR_TILE_AUTO = -1, GBR_TILE_16X16 = 0, GBR_TILE_32X8 = 1, GBR_TILE_8X32 = 2, GBR_TILE_COUNT = 3 };
+
+/* Bind n >= 1 grids and their states for batched stepping.
+ * Every grid must be 2-D, inviscid, static, with limiter GBR_LIM_NONE or
+ * GBR_LIM_MP, and all must share precision, limiter, gamma, the MP
+ * constants, the stream and the device; a grid may appear once. Metrics
+ * must be computed (gbr_metrics) before gbr_batch_run.
+ * Q[b]: device state of grid b, advanced in place by gbr_batch_run; it must
+ * stay allocated until gbr_batch_destroy. The grids' own RK and residual
+ * buffers serve as the two stage buffers, so no other step or RHS call may
+ * run on these grids while the batch has work queued.
+ * tile: GBR_TILE_* or GBR_TILE_AUTO, which times one stage launch of every
+ * shape on this batch (writing only the stage buffers) and keeps the
+ * fastest. Results do not depend on the tile shape up to floating-point
+ * contraction; a caller that needs bitwise equality between batches fixes
+ * the shape.
+ * The library allocates a few bytes per grid and per tile on the device.
+ * Errors: GBR_E_ARG, GBR_E_UNSUPPORTED (a grid outside the requirements),
+ * GBR_E_NOMEM, GBR_E_DEVICE; message in gbr_last_error(g[0]).             */
+gbr_status gbr_batch_create(const gbr_grid *g, int n, double *const *Q, int tile, gbr_batch *out);
+
+/* Enqueue `steps` >= 0 SSP-RK3 steps of every grid of the batch: per grid,
+ * dt from App. B (dt_mode GBR_DT_CFL, cfl_or_dt the CFL number) or dt =
+ * cfl_or_dt (GBR_DT_FIXED), then the three stages. The batch runs on its own
+ * stream, ordered after the work queued on the grids' stream before the
+ * call; work queued there afterwards waits for it. use_graph != 0 captures
+ * one step as a HIP graph on first use (again when cfl_or_dt or dt_mode
+ * change) and replays it. Non-physical states set the grid's flag
+ * (gbr_check_state). Errors: GBR_E_ARG, GBR_E_DEVICE; message in
+ * gbr_last_error of the first grid.                                        */
+gbr_status gbr_batch_run(gbr_batch b, int steps, double cfl_or_dt, int dt_mode, int use_graph);
+
+/* Wait for the batch, then copy, per grid in creation order, the time
+ * accumulated by all steps since creation into t[n] and the last step's dt
+ * into dt[n] (host arrays, each may be NULL), and the tile shape in use
+ * into *tile (may be NULL).                                                */
+gbr_status gbr_batch_query(gbr_batch b, double *t, double *dt, int *tile);
+
+/* Wait for the batch and release it (not the grids). NULL is accepted.     */
+gbr_status gbr_batch_destroy(gbr_batch b);
+
 /* Message for the last error on g (static text for g == NULL). Valid until
  * the next call on g.                                                       */
 const char *gbr_last_error(gbr_grid g);

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "gbr.h"
+
 namespace gbr {
 
 // Periodic index: a in any range, n >= 1.
@@ -140,6 +142,169 @@ __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R
         F[2] += SK * (q2 - r * v);
         F[3] += SK * (q3 - r * w);
         F[4] += SK * (q4 - E);
+    }
+}
+
+// Time-step bound of one cell (App. B): min over the directions d of
+// 1 / (|U_d| + c |grad d|) from the unhatted cell metrics, and, for viscous
+// flow, min_d 1 / (nu |grad d|^2) divided by alpha_D, with nu = mu / rho.
+// The step is dt = CFL * (minimum over all cells).
+template <int NDIM, bool VISC>
+__device__ __forceinline__ double cell_dt_bound(const double *Q, const double *m, long N, long idx, double gamma,
+                                                double gm1, double gM2, double suth, double re, double alpha_d)
+{
+    double r = Q[idx];
+    double u = Q[N + idx] / r, v = Q[2 * N + idx] / r;
+    double w = (NDIM == 3) ? Q[3 * N + idx] / r : 0.0;
+    double p = gm1 * (Q[(NDIM + 1) * N + idx] - 0.5 * r * (u * u + v * v + w * w));
+    double c = sqrt(gamma * p / r);
+    double nu = VISC ? viscosity(gM2 * p / r, suth, re) / r : 0.0;
+    double best = __builtin_inf(), bv = __builtin_inf();
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        double dx = m[GBR_SLOT_CELL_UNHAT(d, 0) * N + idx];
+        double dy = m[GBR_SLOT_CELL_UNHAT(d, 1) * N + idx];
+        double dz = m[GBR_SLOT_CELL_UNHAT(d, 2) * N + idx];
+        double U = m[GBR_SLOT_CELL_UNHATT(d) * N + idx] + dx * u + dy * v + dz * w;
+        double g2 = dx * dx + dy * dy + dz * dz;
+        best = fmin(best, 1.0 / (fabs(U) + c * sqrt(g2)));
+        if (VISC) bv = fmin(bv, 1.0 / (nu * g2));
+    }
+    if (VISC) best = fmin(best, bv / alpha_d);
+    return best;
+}
+
+// Primitive pencils and their first derivatives in LDS: NVL variables at a
+// stride vs. With NVL = 5 they are (rho, u, v, w, p); with NVL = 4 (2-D)
+// they are (rho, u, v, p) and w is identically zero.
+template <int NVL, class R>
+__device__ __forceinline__ R pencil(const R *x, int vs, int v, int o)
+{
+    if (NVL == 4) {
+        if (v == 3) return R(0);
+        if (v == 4) v = 3;
+    }
+    return x[v * vs + o];
+}
+
+// Hermite second derivatives of the four cells a-1 .. a+2 of an interface
+// (Step-1 of Sec. 5.1) from primitives P and first derivatives G of one
+// variable, both pointing at cell a, with stride ST between cells (a
+// constant stride folds into the LDS offsets once inlined).
+template <class R>
+__device__ __forceinline__ void second_derivs(const R *P, const R *G, int ST, R h[4])
+{
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int o = (q - 1) * ST;
+        h[q] = hermite2(P[o - ST], P[o], P[o + ST], G[o - ST], G[o + ST]);
+    }
+}
+
+// Limited interface states of Step-2..Step-5 of Sec. 5.1: characteristic
+// projection with the left eigenvectors of the averaged state and the unit
+// interface normal (App. A), unlimited van Leer states, MP limiter per
+// field (App. E), back projection. P, G point at the pencil primitives and
+// first derivatives of cell a (the left cell), ST is the stride between
+// cells and vsP, vsG the strides between variables.
+template <int NVL, class R>
+__device__ __forceinline__ void limited_states(const R *P, const R *G, int ST, int vsP, int vsG, R nx, R ny, R nz,
+                                               R gamma, R alpha_mp, R beta_mp, R PL[5], R PR[5])
+{
+    const R twelfth = R(1.0 / 12.0);
+    const int ip = (NVL == 4) ? 3 : 4;
+    R rb = R(0.5) * (P[0] + P[ST]);
+    R pb = R(0.5) * (P[ip * vsP] + P[ip * vsP + ST]);
+    R ab2 = gamma * pb / rb;
+    R ra = rb * sqrt(ab2);
+    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
+    R ex = nx * inn, ey = ny * inn, ez = nz * inn;
+    // projection of a primitive vector x:
+    //   W0 = p - ra (e.u),  W4 = p + ra (e.u),
+    //   (W1, W2, W3) = (ex s + (e x u)_x, ez s + (e x u)_z, -ey s - (e x u)_y),
+    //   s = a^2 rho - p
+    auto project = [&](R x0, R x1, R x2, R x3, R x4, R W[5]) {
+        R un = ex * x1 + ey * x2 + ez * x3;
+        R s = ab2 * x0 - x4;
+        W[0] = x4 - ra * un;
+        W[1] = ex * s + (ey * x3 - ez * x2);
+        W[2] = ez * s + (ex * x2 - ey * x1);
+        W[3] = -ey * s - (ez * x1 - ex * x3);
+        W[4] = x4 + ra * un;
+    };
+    auto ld = [&](const R *x, int vs, int v, int o) { return pencil<NVL>(x, vs, v, o); };
+    // cell values W[q] (q = 0..3 -> cells a-1 .. a+2), curvatures W2[q],
+    // first derivatives W1[0..1] (cells a, a+1)
+    R W[4][5], W2[4][5], W1[2][5];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int o = (q - 1) * ST;
+        project(ld(P, vsP, 0, o), ld(P, vsP, 1, o), ld(P, vsP, 2, o), ld(P, vsP, 3, o), ld(P, vsP, 4, o), W[q]);
+    }
+    {
+        R h[5][4];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            if (NVL == 4 && v == 3) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) h[v][q] = R(0);
+            } else {
+                const int vv = (NVL == 4 && v == 4) ? 3 : v;
+                second_derivs(P + vv * vsP, G + vv * vsG, ST, h[v]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) project(h[0][q], h[1][q], h[2][q], h[3][q], h[4][q], W2[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = q * ST;
+        project(ld(G, vsG, 0, o), ld(G, vsG, 1, o), ld(G, vsG, 2, o), ld(G, vsG, 3, o), ld(G, vsG, 4, o), W1[q]);
+    }
+    R WL[5], WR[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        R wl = W[1][v] + R(0.5) * W1[0][v] + twelfth * W2[1][v];
+        R wr = W[2][v] - R(0.5) * W1[1][v] + twelfth * W2[2][v];
+        WL[v] = mp_limit(W[0][v], W[1][v], W[2][v], W2[0][v], W2[1][v], W2[2][v], wl, alpha_mp, beta_mp);
+        WR[v] = mp_limit(W[3][v], W[2][v], W[1][v], W2[3][v], W2[2][v], W2[1][v], wr, alpha_mp, beta_mp);
+    }
+    // right eigenvectors (App. A)
+    R ia2 = R(1) / ab2;
+    R i2ra = R(0.5) / ra;
+    auto back = [&](const R *w, R *x) {
+        R h = (w[4] - w[0]) * i2ra;
+        x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
+        x[1] = ex * h - ey * w[2] - ez * w[3];
+        x[2] = ey * h - ez * w[1] + ex * w[2];
+        x[3] = ez * h + ey * w[1] + ex * w[3];
+        x[4] = R(0.5) * (w[0] + w[4]);
+    };
+    back(WL, PL);
+    back(WR, PR);
+}
+
+// Unlimited van Leer states of Eq. vanleer-poly, formed directly in
+// primitive variables (identical to projecting and back-projecting since
+// R R^-1 = I). Same pointer conventions as limited_states.
+template <int NVL, class R>
+__device__ __forceinline__ void direct_states(const R *P, const R *G, int ST, int vsP, int vsG, R PL[5], R PR[5])
+{
+    const R twelfth = R(1.0 / 12.0);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (NVL == 4 && v == 3) {
+            PL[v] = R(0);
+            PR[v] = R(0);
+            continue;
+        }
+        const int vv = (NVL == 4 && v == 4) ? 3 : v;
+        const R *x = P + vv * vsP;
+        const R *g = G + vv * vsG;
+        R ha = hermite2(x[-ST], x[0], x[ST], g[-ST], g[ST]);
+        R hb = hermite2(x[0], x[ST], x[2 * ST], g[0], g[2 * ST]);
+        PL[v] = x[0] + R(0.5) * g[0] + twelfth * ha;
+        PR[v] = x[ST] - R(0.5) * g[ST] + twelfth * hb;
     }
 }
 

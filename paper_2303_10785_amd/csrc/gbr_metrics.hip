@@ -67,6 +67,8 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
     unpack(a.dm, idx, ijk);
     // Coordinates are measured from the cell's own centre: the metrics are
     // translation invariant and this avoids cancellation of O(|x| / dx).
+    // The periodic image (x + wraps * offset) is formed first, then shifted,
+    // so a window across the seam rounds like one that does not cross it.
     double v[11];
     for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 3; ++c) {
@@ -74,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d, q, &wr);
-                v[q + 5] = (coord(a, c, nb) - org) + wr * a.off[d][c];
+                v[q + 5] = (coord(a, c, nb) + wr * a.off[d][c]) - org;
             }
             a.dx[(d * 3 + c) * a.dm.ncell + idx] = dcomp(v + 5);
         }
@@ -97,13 +99,13 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a)
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d2, q, &wr);
-                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) - org) + wr * a.off[d2][c2]);
+                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d2][c2]) - org);
             }
             double ta = dcomp(v + 5);
             for (int q = -5; q <= 5; ++q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d1, q, &wr);
-                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) - org) + wr * a.off[d1][c2]);
+                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d1][c2]) - org);
             }
             hat[d][c] = ta - dcomp(v + 5);
         }

@@ -205,92 +205,6 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
     return pack(dm, t[0], t[1], t[2]);
 }
 
-// Hermite second derivatives of the four cells a-1 .. a+2 of an interface
-// (Step-1 of Sec. 5.1) from the LDS primitives P (pointer at cell a) and
-// first derivatives G (pointer at cell a), one variable at stride ST.
-template <int ST, class R>
-__device__ __forceinline__ void second_derivs(const R *P, const R *G, R h[4])
-{
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int o = (q - 1) * ST;
-        h[q] = hermite2(P[o - ST], P[o], P[o + ST], G[o - ST], G[o + ST]);
-    }
-}
-
-// Limited interface states of Step-2..Step-5 of Sec. 5.1: characteristic
-// projection with the left eigenvectors of the averaged state and the unit
-// interface normal (App. A), unlimited van Leer states, MP limiter per
-// field (App. E), back projection. P, G point at the LDS primitives and first
-// derivatives of cell a (the left cell); vsP, vsG are the variable strides.
-template <int D, class R>
-__device__ __forceinline__ void limited_states(const R *P, const R *G, int vsP, int vsG, R nx, R ny, R nz,
-                                               const PhysR<R> &ph, R PL[5], R PR[5])
-{
-    constexpr int st = Tile<D>::ST;
-    const R twelfth = R(1.0 / 12.0);
-    R rb = R(0.5) * (P[0] + P[st]);
-    R pb = R(0.5) * (P[4 * vsP] + P[4 * vsP + st]);
-    R ab2 = ph.gamma * pb / rb;
-    R ra = rb * sqrt(ab2);
-    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
-    R ex = nx * inn, ey = ny * inn, ez = nz * inn;
-    // projection of a primitive vector x:
-    //   W0 = p - ra (e.u),  W4 = p + ra (e.u),
-    //   (W1, W2, W3) = (ex s + (e x u)_x, ez s + (e x u)_z, -ey s - (e x u)_y),
-    //   s = a^2 rho - p
-    auto project = [&](R x0, R x1, R x2, R x3, R x4, R W[5]) {
-        R un = ex * x1 + ey * x2 + ez * x3;
-        R s = ab2 * x0 - x4;
-        W[0] = x4 - ra * un;
-        W[1] = ex * s + (ey * x3 - ez * x2);
-        W[2] = ez * s + (ex * x2 - ey * x1);
-        W[3] = -ey * s - (ez * x1 - ex * x3);
-        W[4] = x4 + ra * un;
-    };
-    // cell values W[q] (q = 0..3 -> cells a-1 .. a+2), curvatures W2[q],
-    // first derivatives W1[0..1] (cells a, a+1)
-    R W[4][5], W2[4][5], W1[2][5];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int o = (q - 1) * st;
-        project(P[o], P[vsP + o], P[2 * vsP + o], P[3 * vsP + o], P[4 * vsP + o], W[q]);
-    }
-    {
-        R h[5][4];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) second_derivs<st>(P + v * vsP, G + v * vsG, h[v]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) project(h[0][q], h[1][q], h[2][q], h[3][q], h[4][q], W2[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int o = q * st;
-        project(G[o], G[vsG + o], G[2 * vsG + o], G[3 * vsG + o], G[4 * vsG + o], W1[q]);
-    }
-    R WL[5], WR[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        R wl = W[1][v] + R(0.5) * W1[0][v] + twelfth * W2[1][v];
-        R wr = W[2][v] - R(0.5) * W1[1][v] + twelfth * W2[2][v];
-        WL[v] = mp_limit(W[0][v], W[1][v], W[2][v], W2[0][v], W2[1][v], W2[2][v], wl, ph.alpha_mp, ph.beta_mp);
-        WR[v] = mp_limit(W[3][v], W[2][v], W[1][v], W2[3][v], W2[2][v], W2[1][v], wr, ph.alpha_mp, ph.beta_mp);
-    }
-    // right eigenvectors (App. A)
-    R ia2 = R(1) / ab2;
-    R i2ra = R(0.5) / ra;
-    auto back = [&](const R *w, R *x) {
-        R h = (w[4] - w[0]) * i2ra;
-        x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
-        x[1] = ex * h - ey * w[2] - ez * w[3];
-        x[2] = ey * h - ez * w[1] + ex * w[2];
-        x[3] = ez * h + ey * w[1] + ex * w[3];
-        x[4] = R(0.5) * (w[0] + w[4]);
-    };
-    back(WL, PL);
-    back(WR, PR);
-}
-
 template <int D, int NDIM, bool VISC, bool FIRST, class R>
 __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
 {
@@ -311,7 +225,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     const int c0 = tcb * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
-    const R twelfth = R(1.0 / 12.0);
 
     // Phase 1: primitives of cells s0-6 .. s0+TS+4 into LDS
     for (int e = tid; e < VP; e += kBlock) {
@@ -339,9 +252,40 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     }
     __syncthreads();
 
-    // Phase 3: one interface per thread, between cells a = s0+t-1 and a+1.
-    const int t = T::t_of(tid);
-    const int cl = T::c_of(tid);
+    // Phase 3: one interface per thread. Interface f (f = thread id of its
+    // home lane) lies between cells a = s0+t-1 and a+1 with t = t_of(f).
+    // With the Ducros gate the flagged interfaces of the tile are gathered
+    // onto the first lanes, so whole wavefronts run either the limited or
+    // the direct states instead of both under a mask.
+    int f = tid;
+    bool limited = ph.limiter == GBR_LIM_MP;
+    if (ph.limiter == GBR_LIM_DUCROS) {
+        __shared__ int s_order[kBlock];
+        __shared__ int s_count[kBlock / 64];
+        const int t0 = T::t_of(tid), cl0 = T::c_of(tid);
+        const int cg0 = min(c0 + cl0, nc - 1);
+        const long a0 = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t0 - 1, ns), cg0, o);
+        const long b0 = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t0, ns), cg0, o);
+        const bool mine = fmax(a.theta[a0], a.theta[b0]) > ph.theta_c;
+        const unsigned long long bal = __ballot(mine);
+        const int lane = tid % 64, wave = tid / 64;
+        const int below = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) s_count[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            before += (w < wave) ? s_count[w] : 0;
+            total += s_count[w];
+        }
+        const int lim_rank = before + below;  // flagged interfaces on lower lanes
+        s_order[mine ? lim_rank : total + (tid - lim_rank)] = tid;
+        __syncthreads();
+        f = s_order[tid];
+        limited = tid < total;
+    }
+    const int t = T::t_of(f);
+    const int cl = T::c_of(f);
     const int cg = c0 + cl;
     const int cgc = min(cg, nc - 1);
     const long ca = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t - 1, ns), cgc, o);
@@ -349,26 +293,14 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     const R *Pa = sP + T::at(t + 5, cl, NP);
     const R *Ga = s1 + T::at(t + 2, cl, N1);
     const double *m = a.m;
-    bool limited = ph.limiter == GBR_LIM_MP;
-    if (ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     R PL[5], PR[5];
     if (limited) {
         R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
         R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
         R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
-        limited_states<D>(Pa, Ga, VP, V1, nx, ny, nz, ph, PL, PR);
+        limited_states<5>(Pa, Ga, st, VP, V1, nx, ny, nz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
     } else {
-        // Unlimited states of Eq. vanleer-poly directly in primitive form
-        // (identical to projecting and back-projecting since R R^-1 = I).
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const R *x = Pa + v * VP;
-            const R *g = Ga + v * V1;
-            R ha = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
-            R hb = hermite2(x[0], x[st], x[2 * st], g[0], g[2 * st]);
-            PL[v] = x[0] + R(0.5) * g[0] + twelfth * ha;
-            PR[v] = x[st] - R(0.5) * g[st] + twelfth * hb;
-        }
+        direct_states<5>(Pa, Ga, st, VP, V1, PL, PR);
     }
     if (NDIM == 2) {
         PL[3] = R(0);
@@ -447,14 +379,18 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
 #pragma unroll
     for (int v = 0; v < 5; ++v) sP[v * kBlock + T::at(t, cl, TS)] = phi[v];
     __syncthreads();
-    // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7)
-    if (t < TS - 1 && s0 + t < ns && cg < nc) {
+    // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7),
+    // with t and the cross lane of this thread's home position
+    const int th = T::t_of(tid), clh = T::c_of(tid);
+    const int cgh = c0 + clh;
+    if (th < TS - 1 && s0 + th < ns && cgh < nc) {
+        const long ch = cell_of(dm, T::SD, T::CD, s0 + th, cgh, o);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
             const int ov = (NDIM == 2 && v == 4) ? 3 : v;
-            const R d = sP[v * kBlock + T::at(t + 1, cl, TS)] - sP[v * kBlock + T::at(t, cl, TS)];
-            R *r = a.res + (long)ov * N + cb;
+            const R d = sP[v * kBlock + T::at(th + 1, clh, TS)] - sP[v * kBlock + T::at(th, clh, TS)];
+            R *r = a.res + (long)ov * N + ch;
             if (FIRST)
                 *r = -d;
             else
@@ -496,25 +432,8 @@ __global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const 
     const long N = dm.ncell;
     double best = __builtin_inf();
     for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
-        double r = Q[idx];
-        double ir = 1.0 / r;
-        double u = Q[N + idx] * ir, v = Q[2 * N + idx] * ir;
-        double w = (NDIM == 3) ? Q[3 * N + idx] * ir : 0.0;
-        double p = ph.gm1 * (Q[(NDIM + 1) * N + idx] - 0.5 * r * (u * u + v * v + w * w));
-        double c = sqrt(ph.gamma * p * ir);
-        double nu = VISC ? viscosity(ph.gM2 * p / r, ph.suth, ph.re) / r : 0.0;
-        double bv = __builtin_inf();
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-            double dx = m[GBR_SLOT_CELL_UNHAT(d, 0) * N + idx];
-            double dy = m[GBR_SLOT_CELL_UNHAT(d, 1) * N + idx];
-            double dz = m[GBR_SLOT_CELL_UNHAT(d, 2) * N + idx];
-            double U = m[GBR_SLOT_CELL_UNHATT(d) * N + idx] + dx * u + dy * v + dz * w;
-            double g2 = dx * dx + dy * dy + dz * dz;
-            best = fmin(best, 1.0 / (fabs(U) + c * sqrt(g2)));
-            if (VISC) bv = fmin(bv, 1.0 / (nu * g2));
-        }
-        if (VISC) best = fmin(best, bv / ph.alpha_d);
+        best = fmin(best, cell_dt_bound<NDIM, VISC>(Q, m, N, idx, ph.gamma, ph.gm1, ph.gM2, ph.suth, ph.re,
+                                                        ph.alpha_d));
     }
     // wavefront minimum, then across the block's wavefronts
     for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
@@ -583,7 +502,8 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a)
         Timed timed(g, GBR_K_PRIMS);
         hipLaunchKernelGGL((k_prims<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     }
-    {
+    // cell gradients feed only the tangential viscous terms and the sensor
+    if (VISC || a.pr.limiter == GBR_LIM_DUCROS) {
         Timed timed(g, GBR_K_CELL_GRAD);
         dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
                 unsigned((a.dm.n[2] + KC - 1) / KC));
@@ -591,9 +511,8 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a)
             hipLaunchKernelGGL((k_cell_grad<NDIM, true, R>), gg, dim3(kBlock), 0, g->stream, a);
         else
             hipLaunchKernelGGL((k_cell_grad<NDIM, false, R>), gg, dim3(kBlock), 0, g->stream, a);
-        e = hipGetLastError();
     }
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = sweep<0, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
     if ((e = sweep<1, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
     if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R>(g, a);

@@ -21,6 +21,8 @@ LIM = {"none": 0, "mp": 1, "ducros": 2}
 GBR_FP64, GBR_FP32_BULK = 0, 1
 PRECISION = {"fp64": GBR_FP64, "fp32_bulk": GBR_FP32_BULK}
 GBR_DT_CFL, GBR_DT_FIXED = 0, 1
+GBR_TILE_AUTO, GBR_TILE_16X16, GBR_TILE_32X8, GBR_TILE_8X32 = -1, 0, 1, 2
+TILE_NAMES = {0: "16x16", 1: "32x8", 2: "8x32"}
 
 
 def SLOT_FACE_HAT(f, c):
@@ -119,9 +121,14 @@ def lib():
     L.gbr_timing_collect.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     L.gbr_last_error.argtypes = [_VP]
     L.gbr_last_error.restype = C.c_char_p
+    L.gbr_batch_create.argtypes = [_PP, C.c_int, _PP, C.c_int, C.POINTER(_VP)]
+    L.gbr_batch_run.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.c_int]
+    L.gbr_batch_query.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.gbr_batch_destroy.argtypes = [_VP]
     for nm in ("gbr_grid_create", "gbr_grid_destroy", "gbr_set_stream", "gbr_metrics", "gbr_rhs",
                "gbr_rk_stage", "gbr_cfl", "gbr_step", "gbr_check_state", "gbr_timing_enable",
-               "gbr_timing_collect"):
+               "gbr_timing_collect", "gbr_batch_create", "gbr_batch_run", "gbr_batch_query",
+               "gbr_batch_destroy"):
         getattr(L, nm).restype = C.c_int
     _lib = L
     return L
@@ -260,6 +267,32 @@ def gbr_last_error(h):
     return lib().gbr_last_error(h).decode()
 
 
+def gbr_batch_create(handles, Q, tile=GBR_TILE_AUTO):
+    n = len(handles)
+    b = C.c_void_p()
+    _check(lib().gbr_batch_create(_arr(handles), n, _arr(Q), int(tile), C.byref(b)),
+           handles[0] if n else None)
+    return b
+
+
+def gbr_batch_run(b, steps, cfl_or_dt, dt_mode=GBR_DT_CFL, use_graph=True, err_handle=None):
+    _check(lib().gbr_batch_run(b, int(steps), float(cfl_or_dt), int(dt_mode), int(bool(use_graph))),
+           err_handle)
+
+
+def gbr_batch_query(b, n, err_handle=None):
+    """(t, dt, tile): per-grid accumulated time and last dt (host lists)."""
+    t = (C.c_double * n)()
+    dt = (C.c_double * n)()
+    tile = C.c_int()
+    _check(lib().gbr_batch_query(b, t, dt, C.byref(tile)), err_handle)
+    return list(t), list(dt), tile.value
+
+
+def gbr_batch_destroy(b):
+    _check(lib().gbr_batch_destroy(b))
+
+
 # ---------------------------------------------------------------------------
 # convenience wrapper over one grid
 # ---------------------------------------------------------------------------
@@ -350,3 +383,32 @@ def _memcpy_d2d(dst, src, nbytes):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 3)  # device to device
     if rc != 0:
         raise GbrError(GBR_E_DEVICE, f"hipMemcpy failed ({rc})")
+
+
+class Batch:
+    """Batched stepping of several 2-D Euler ``Grid`` objects whose metrics
+    are computed; ``Q`` are their device states (advanced in place)."""
+
+    def __init__(self, grids, Q, tile=GBR_TILE_AUTO):
+        self.grids = list(grids)
+        self.Q = list(Q)
+        self.n = len(self.grids)
+        self.h0 = self.grids[0].h if self.grids else None
+        self.b = gbr_batch_create([g.h for g in self.grids], self.Q, tile)
+
+    def run(self, steps, cfl_or_dt, dt_mode=GBR_DT_CFL, graph=True):
+        gbr_batch_run(self.b, steps, cfl_or_dt, dt_mode, graph, self.h0)
+
+    def query(self):
+        return gbr_batch_query(self.b, self.n, self.h0)
+
+    def close(self):
+        if self.b:
+            gbr_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,6 +63,15 @@ def test_null_arguments_rejected_without_device_work():
     assert L.gbr_check_state(None) == gbr.GBR_E_ARG
     assert L.gbr_last_error(None) == b"null grid handle"
     assert L.gbr_metric_ptr(None, 0) is None
+    # batched stepping
+    b = C.c_void_p()
+    assert L.gbr_batch_create(None, 1, None, -1, C.byref(b)) == gbr.GBR_E_ARG
+    assert L.gbr_batch_create(None, 0, None, -1, C.byref(b)) == gbr.GBR_E_ARG
+    assert L.gbr_batch_create(None, 1, None, -1, None) == gbr.GBR_E_ARG
+    assert b.value is None
+    assert L.gbr_batch_run(None, 1, 0.4, 0, 1) == gbr.GBR_E_ARG
+    assert L.gbr_batch_query(None, None, None, None) == gbr.GBR_E_ARG
+    assert L.gbr_batch_destroy(None) == gbr.GBR_OK
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

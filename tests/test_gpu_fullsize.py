@@ -34,7 +34,13 @@ def say(*a):
     print(*a, flush=True)
 
 
+def rel_whole(gpu, ref):
+    """Max error over the whole RHS relative to its largest component."""
+    return float(np.abs(gpu - ref).max()) / float(np.abs(ref).max())
+
+
 def rel(gpu, ref):
+    """Max over variables of the error relative to that variable's scale."""
     worst = 0.0
     for v in range(ref.shape[0]):
         s = float(np.abs(ref[v]).max())
@@ -126,7 +132,9 @@ def _config2():
 
 def test_config2_rhs_full(gbr):
     """128^3 deforming randomized grid, uniform Mach 0.5 NS flow: one RHS
-    (dominated by the GCL term) matches the oracle."""
+    (dominated by the GCL term) matches the oracle. The rho v and rho w
+    components vanish exactly for this flow (both sides hold round-off
+    only), so the error is taken relative to the largest RHS component."""
     mv = _config2()
     g = mv.at(0.1)
     pinf = 1.0 / (1.4 * 0.25)
@@ -143,7 +151,7 @@ def test_config2_rhs_full(gbr):
     m = oracle.metrics(g, **C2_PARAMS)
     ref = oracle.rhs(g, m, Q, **C2_PARAMS)
     got = res.cpu().numpy()
-    e = rel(got, ref)
+    e = rel_whole(got, ref)
     bal = np.abs(jac * (got - ijt * Q)).max()
     say(f"[config2 rhs] max rel err {e:.3e}; |J (Res - (1/J)_t Q)| max {bal:.3e}")
     assert e <= TOL

@@ -337,3 +337,46 @@ def random_rough_state(grid, seed=0, amp=0.3, gamma=1.4):
     w = 0.1 + amp * rng.uniform(-1, 1, shp) if grid["ndim"] == 3 else np.zeros(shp)
     p = 1.0 + amp * rng.uniform(-1, 1, shp)
     return conserved(rho, u, v, w, p, gamma, grid["ndim"])
+
+
+def vortex_sod(grid, eps=2.0, xc=None, yc=None, gamma=1.4):
+    """Sod-type (rho, p) = (1, 1) | (0.125, 0.1) split at x = L/2 (periodic, so
+    a second jump sits at the seam), with an isentropic vortex of strength eps
+    superposed: vortex velocities and the vortex's isentropic density and
+    pressure factors on top of the Sod state. Cells whose centre lies on the
+    split (within 1e-9 L; odd N puts a whole column there) take the right
+    state, so round-off in the coordinates cannot make that column zigzag."""
+    L = grid["off"][0][0]
+    xc = 0.5 * L if xc is None else xc
+    yc = 0.5 * grid["off"][1][1] if yc is None else yc
+    x, y = grid["xyz"][0], grid["xyz"][1]
+    dx, dy = x - xc, y - yc
+    f = np.exp(0.5 * (1.0 - (dx * dx + dy * dy)))
+    u = -eps / (2 * np.pi) * f * dy
+    v = eps / (2 * np.pi) * f * dx
+    T = 1.0 - (gamma - 1.0) * eps * eps / (8 * gamma * np.pi ** 2) * f * f
+    left = x < 0.5 * L - 1e-9 * L
+    rho = np.where(left, 1.0, 0.125) * T ** (1.0 / (gamma - 1.0))
+    p = np.where(left, 1.0, 0.1) * T ** (gamma / (gamma - 1.0))
+    return conserved(rho, u, v, np.zeros_like(u), p, gamma, grid["ndim"])
+
+
+def batch2d(count=256, seed=4, log2_min=5.0, log2_max=9.0, L=10.0):
+    """Many-small-grids workload: ``count`` square periodic wavy grids with
+    N = round(2^U(log2_min, log2_max)) cells per side and mapping amplitude
+    U(0.02, 0.1) (fraction of L); even-numbered draws carry a Shu vortex
+    (eps 5 at the centre, freestream (1, 1, 1, 1)), odd ones the Sod-type
+    state with an eps = 2 vortex. Returns a list of (grid, Q, kind)."""
+    rng = np.random.default_rng(SEED_BASE + seed)
+    out = []
+    for b in range(count):
+        n = int(round(2.0 ** rng.uniform(log2_min, log2_max)))
+        amp = float(rng.uniform(0.02, 0.1))
+        vortex = rng.uniform() < 0.5
+        g = wavy2d((n, n), L=L, amp=amp)
+        if vortex:
+            Q = shu_vortex(g, eps=5.0, xc=0.5 * L, yc=0.5 * L)
+        else:
+            Q = vortex_sod(g)
+        out.append((g, Q, "vortex" if vortex else "sod"))
+    return out
