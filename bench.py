@@ -43,7 +43,9 @@ ALG_BYTES_PER_CELL = {
     "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40,   # 5 primitives + T, 12 face metrics, 8 tangential
                                              # grads, T', theta -> Res out
     "sweep_eta": 48 + 96 + 64 + 8 + 8 + 80,  # ... Res in and out
-    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 80,
+    # last sweep with the SSP-RK3 stage fused: Res in; Q, Qn, J, (1/J)_t in;
+    # Q out; the next stage's primitives out in two of the three stages
+    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 40 + 96 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     "cfl": 40 + 72 + 24,                  # Q, 9 cell metrics, 3 temporal metrics
     "copy": 80,

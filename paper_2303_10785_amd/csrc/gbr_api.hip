@@ -93,7 +93,7 @@ size_t bytes_for(const gbr_config *c)
 {
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     size_t nv = (size_t)c->ndim + 2;
-    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 6 + 2 * nv) + 1 + gbr::kReducePartials;
+    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 12 + 2 * nv) + 1 + gbr::kReducePartials;
     return doubles * sizeof(double) + sizeof(unsigned long long) + 2 * sizeof(int);
 }
 
@@ -128,7 +128,7 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->prim,
+    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->prim, (void *)g->prim2,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
@@ -176,6 +176,7 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     alloc((void **)&g->scratch, N * 12 * sizeof(double));
     alloc((void **)&g->theta, N * sizeof(double));
     alloc((void **)&g->prim, N * 6 * sizeof(double));
+    alloc((void **)&g->prim2, N * 6 * sizeof(double));
     alloc((void **)&g->partial, gbr::kReducePartials * sizeof(double));
     alloc((void **)&g->qn, N * g->nvar * sizeof(double));
     alloc((void **)&g->res, N * g->nvar * sizeof(double));
@@ -308,10 +309,7 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
         }
         const long nq = (long)gg->nvar * gg->ncell;
         if (e == hipSuccess) e = gbr::launch_copy(gg, gg->qn, Q[b], nq);
-        for (int st = 0; st < 3 && e == hipSuccess; ++st) {
-            e = gbr::launch_rhs(gg, Q[b], gg->res);
-            if (e == hipSuccess) e = gbr::launch_rk_stage(gg, st, gg->dt, gg->qn, Q[b], gg->res);
-        }
+        for (int st = 0; st < 3 && e == hipSuccess; ++st) e = gbr::launch_step_stage(gg, st, gg->dt, gg->qn, Q[b]);
         if (e == hipSuccess && dt_out && dt_out[b]) e = gbr::launch_copy(gg, dt_out[b], gg->dt, 1);
         if (e != hipSuccess) return hip_fail(gg, e, "step launch");
     }

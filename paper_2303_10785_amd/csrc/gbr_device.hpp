@@ -308,4 +308,109 @@ __device__ __forceinline__ void direct_states(const R *P, const R *G, int ST, in
     }
 }
 
+// Limited interface states as in limited_states, with the Hermite second
+// derivatives precomputed per cell (H, variable stride vsH, same cell
+// indexing as P). The characteristic fields are formed and limited in small
+// groups straight from the pencils, (W0, W4) together and W1, W2, W3 one at
+// a time, so few projected values are live at once.
+template <int NVL, class R>
+__device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const R *H, int ST, int vsP, int vsG,
+                                                   int vsH, R nx, R ny, R nz, R gamma, R alpha_mp, R beta_mp,
+                                                   R PL[5], R PR[5])
+{
+    const R twelfth = R(1.0 / 12.0);
+    const int ip = (NVL == 4) ? 3 : 4;
+    R rb = R(0.5) * (P[0] + P[ST]);
+    R pb = R(0.5) * (P[ip * vsP] + P[ip * vsP + ST]);
+    R ab2 = gamma * pb / rb;
+    R ra = rb * sqrt(ab2);
+    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
+    R ex = nx * inn, ey = ny * inn, ez = nz * inn;
+    auto ld = [&](const R *x, int vs, int v, int o) { return pencil<NVL>(x, vs, v, o); };
+    // point k = 0..3: cells a-1 .. a+2 (values and curvatures), k = 0..1:
+    // cells a, a+1 (first derivatives)
+    R WL[5], WR[5];
+    auto limit = [&](int v, const R w[4], const R d[4], const R g[2]) {
+        R wl = w[1] + R(0.5) * g[0] + twelfth * d[1];
+        R wr = w[2] - R(0.5) * g[1] + twelfth * d[2];
+        WL[v] = mp_limit(w[0], w[1], w[2], d[0], d[1], d[2], wl, alpha_mp, beta_mp);
+        WR[v] = mp_limit(w[3], w[2], w[1], d[3], d[2], d[1], wr, alpha_mp, beta_mp);
+    };
+    {
+        // W0 = p - ra (e.u), W4 = p + ra (e.u)
+        R w0[4], w4[4], d0[4], d4[4], g0[2], g4[2];
+        auto acoustic = [&](const R *x, int vs, int o, R &m, R &p) {
+            R un = ex * ld(x, vs, 1, o) + ey * ld(x, vs, 2, o) + ez * ld(x, vs, 3, o);
+            R x4 = ld(x, vs, 4, o);
+            m = x4 - ra * un;
+            p = x4 + ra * un;
+        };
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            acoustic(P, vsP, (k - 1) * ST, w0[k], w4[k]);
+            acoustic(H, vsH, (k - 1) * ST, d0[k], d4[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) acoustic(G, vsG, k * ST, g0[k], g4[k]);
+        limit(0, w0, d0, g0);
+        limit(4, w4, d4, g4);
+    }
+    // W1 = ex s + (ey w - ez v), W2 = ez s + (ex v - ey u),
+    // W3 = -ey s - (ez u - ex w), s = a^2 rho - p
+    auto entropy_shear = [&](int v, const R *x, int vs, int o) {
+        R s = ab2 * ld(x, vs, 0, o) - ld(x, vs, 4, o);
+        R u = ld(x, vs, 1, o), vv = ld(x, vs, 2, o), w = ld(x, vs, 3, o);
+        if (v == 1) return ex * s + (ey * w - ez * vv);
+        if (v == 2) return ez * s + (ex * vv - ey * u);
+        return -ey * s - (ez * u - ex * w);
+    };
+#pragma unroll
+    for (int v = 1; v <= 3; ++v) {
+        R w[4], d[4], g[2];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = entropy_shear(v, P, vsP, (k - 1) * ST);
+            d[k] = entropy_shear(v, H, vsH, (k - 1) * ST);
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) g[k] = entropy_shear(v, G, vsG, k * ST);
+        limit(v, w, d, g);
+    }
+    // right eigenvectors (App. A)
+    R ia2 = R(1) / ab2;
+    R i2ra = R(0.5) / ra;
+    auto back = [&](const R *w, R *x) {
+        R h = (w[4] - w[0]) * i2ra;
+        x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
+        x[1] = ex * h - ey * w[2] - ez * w[3];
+        x[2] = ey * h - ez * w[1] + ex * w[2];
+        x[3] = ez * h + ey * w[1] + ex * w[3];
+        x[4] = R(0.5) * (w[0] + w[4]);
+    };
+    back(WL, PL);
+    back(WR, PR);
+}
+
+// Unlimited van Leer states with precomputed curvatures (see direct_states).
+template <int NVL, class R>
+__device__ __forceinline__ void direct_states_pre(const R *P, const R *G, const R *H, int ST, int vsP, int vsG,
+                                                  int vsH, R PL[5], R PR[5])
+{
+    const R twelfth = R(1.0 / 12.0);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        if (NVL == 4 && v == 3) {
+            PL[v] = R(0);
+            PR[v] = R(0);
+            continue;
+        }
+        const int vv = (NVL == 4 && v == 4) ? 3 : v;
+        const R *x = P + vv * vsP;
+        const R *g = G + vv * vsG;
+        const R *h = H + vv * vsH;
+        PL[v] = x[0] + R(0.5) * g[0] + twelfth * h[0];
+        PR[v] = x[ST] - R(0.5) * g[ST] + twelfth * h[ST];
+    }
+}
+
 }  // namespace gbr

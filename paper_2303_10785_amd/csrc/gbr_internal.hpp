@@ -19,6 +19,7 @@ struct gbr_grid_s {
     double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
     double *theta = nullptr;     // ncell: shock sensor
     double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
+    double *prim2 = nullptr;     // 6 * ncell: second primitive buffer (gbr_step stages alternate)
     double *partial = nullptr;   // kReducePartials: per-block minima of the time-step reduction
     double *qn = nullptr;        // nvar * ncell: RK stage-0 state (gbr_step)
     double *res = nullptr;       // nvar * ncell: RHS (gbr_step; float data in FP32-bulk)
@@ -79,6 +80,8 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
 hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res);
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
                            double *Q, const void *res);
+// RHS and SSP-RK3 stage of gbr_step with the stage fused into the last sweep.
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);

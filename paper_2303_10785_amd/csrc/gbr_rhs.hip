@@ -33,6 +33,9 @@ namespace gbr {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef GBR_TS_CROSS
+#define GBR_TS_CROSS 16
+#endif
 
 template <class R>
 struct PhysR {
@@ -52,6 +55,12 @@ struct RhsArgs {
     R *prim;       // 6 * ncell: rho, u, v, w, p, T
     const double *m;  // metrics (always double)
     int *flags;
+    // SSP-RK3 stage fused into the last sweep (gbr_step only)
+    double *Qw;        // state updated in place
+    const double *Qn;  // stage-0 state
+    const double *dt;  // time step (device)
+    double ca, cb;     // stage coefficients
+    R *prim_out;       // primitives of the updated state for the next stage, or null
 };
 
 __device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
@@ -180,13 +189,14 @@ template <int D>
 struct Tile {
     // faces per tile along D, lanes across, and index roles:
     // s = sweep direction D, c = cross direction, o = outer direction.
-    static constexpr int TS = (D == 0) ? 64 : 16;
+    static constexpr int TS = (D == 0) ? 64 : GBR_TS_CROSS;
     static constexpr int TC = kBlock / TS;
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
     static constexpr int OD = (D == 2) ? 1 : 2;
     static constexpr int NP = TS + 11;  // primitive cells s0-6 .. s0+TS+4
     static constexpr int N1 = TS + 5;   // first derivatives s0-3 .. s0+TS+1
+    static constexpr int N2 = TS + 3;   // second derivatives s0-2 .. s0+TS
     static constexpr int ST = (D == 0) ? 1 : TC;  // LDS stride between cells along D
     // LDS offset of (s, c) in an array with ns entries along s: s fastest for
     // the xi sweep (lanes run along s), c fastest otherwise (lanes run along c).
@@ -205,14 +215,22 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
     return pack(dm, t[0], t[1], t[2]);
 }
 
-template <int D, int NDIM, bool VISC, bool FIRST, class R>
-__global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
+#ifdef GBR_SWEEP_MINWAVES
+#define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock, GBR_SWEEP_MINWAVES)
+#else
+#define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock)
+#endif
+// MODE: 0 writes Res, 1 adds to Res, 2 adds to Res and applies the SSP-RK3
+// stage to the tile's own cells (the last sweep of a gbr_step stage).
+template <int D, int NDIM, bool VISC, int MODE, class R>
+__global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
 {
     using T = Tile<D>;
-    constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, st = T::ST;
-    constexpr int VP = NP * TC, V1 = N1 * TC;
+    constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, N2 = T::N2, st = T::ST;
+    constexpr int VP = NP * TC, V1 = N1 * TC, V2 = N2 * TC;
     __shared__ R sP[5 * VP];
     __shared__ R s1[5 * V1];
+    __shared__ R s2[5 * V2];
 
     const Dims &dm = a.dm;
     const PhysR<R> &ph = a.pr;
@@ -251,6 +269,21 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
         }
     }
     __syncthreads();
+    // Hermite second derivatives (Step-1) of cells s0-2 .. s0+TS, once per cell
+    for (int e = tid; e < V2; e += kBlock) {
+        int sl = (D == 0) ? e % N2 : e / TC;
+        int cl = (D == 0) ? e / N2 : e % TC;
+        int pc = T::at(sl + 4, cl, NP);
+        int gc = T::at(sl + 1, cl, N1);
+        int at = T::at(sl, cl, N2);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            const R *x = sP + v * VP + pc;
+            const R *g = s1 + v * V1 + gc;
+            s2[v * V2 + at] = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
+        }
+    }
+    __syncthreads();
 
     // Phase 3: one interface per thread. Interface f (f = thread id of its
     // home lane) lies between cells a = s0+t-1 and a+1 with t = t_of(f).
@@ -259,7 +292,10 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     // the direct states instead of both under a mask.
     int f = tid;
     bool limited = ph.limiter == GBR_LIM_MP;
-    if (ph.limiter == GBR_LIM_DUCROS) {
+    // (FP64 only: in FP32 the scattered LDS reads cost more than the
+    // divergence they remove)
+    constexpr bool compact = sizeof(R) == 8;
+    if (compact && ph.limiter == GBR_LIM_DUCROS) {
         __shared__ int s_order[kBlock];
         __shared__ int s_count[kBlock / 64];
         const int t0 = T::t_of(tid), cl0 = T::c_of(tid);
@@ -292,15 +328,17 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     const long cb = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t, ns), cgc, o);
     const R *Pa = sP + T::at(t + 5, cl, NP);
     const R *Ga = s1 + T::at(t + 2, cl, N1);
+    const R *Ha = s2 + T::at(t + 1, cl, N2);
     const double *m = a.m;
+    if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     R PL[5], PR[5];
     if (limited) {
         R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
         R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
         R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
-        limited_states<5>(Pa, Ga, st, VP, V1, nx, ny, nz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
+        limited_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, nx, ny, nz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
     } else {
-        direct_states<5>(Pa, Ga, st, VP, V1, PL, PR);
+        direct_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, PL, PR);
     }
     if (NDIM == 2) {
         PL[3] = R(0);
@@ -385,16 +423,50 @@ __global__ void __launch_bounds__(kBlock) k_sweep(RhsArgs<R> a)
     const int cgh = c0 + clh;
     if (th < TS - 1 && s0 + th < ns && cgh < nc) {
         const long ch = cell_of(dm, T::SD, T::CD, s0 + th, cgh, o);
+        double qnew[5];
+        double dt = 0.0, J = 0.0, it = 0.0;
+        if (MODE == 2) {
+            dt = *a.dt;
+            J = a.m[GBR_SLOT_CELL_J * N + ch];
+            it = a.m[GBR_SLOT_CELL_INVJT * N + ch];
+        }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
             const int ov = (NDIM == 2 && v == 4) ? 3 : v;
             const R d = sP[v * kBlock + T::at(th + 1, clh, TS)] - sP[v * kBlock + T::at(th, clh, TS)];
             R *r = a.res + (long)ov * N + ch;
-            if (FIRST)
+            if (MODE == 0) {
                 *r = -d;
-            else
+            } else if (MODE == 1) {
                 *r = *r - d;
+            } else {
+                // App. B with Eq. time-split: Q <- a Qn + b (Q + dt J (Res - (1/J)_t Q))
+                const R res = *r - d;
+                const long e = (long)ov * N + ch;
+                const double q = a.Qw[e];
+                const double L = J * (double(res) - it * q);
+                qnew[ov] = a.ca * a.Qn[e] + a.cb * (q + dt * L);
+                a.Qw[e] = qnew[ov];
+            }
+        }
+        if (MODE == 2 && a.prim_out) {
+            // primitives of the new state for the next stage (as k_prims)
+            const double r = qnew[0];
+            const double u = qnew[1] / r;
+            const double v = qnew[2] / r;
+            const double w = (NDIM == 3) ? qnew[3] / r : 0.0;
+            const double E = qnew[NDIM + 1];
+            const double p = a.ph.gm1 * (E - 0.5 * r * (u * u + v * v + w * w));
+            const double T = a.ph.gM2 * p / r;
+            a.prim_out[ch] = R(r);
+            a.prim_out[N + ch] = R(u);
+            a.prim_out[2 * N + ch] = R(v);
+            a.prim_out[3 * N + ch] = R(w);
+            a.prim_out[4 * N + ch] = R(p);
+            a.prim_out[5 * N + ch] = R(T);
+            if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)))
+                atomicOr(a.flags, 1);
         }
     }
 }
@@ -478,7 +550,7 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
 }
 
 template <int D, int NDIM, bool VISC, class R>
-hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a)
+hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
 {
     using T = Tile<D>;
     const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
@@ -487,18 +559,22 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a)
     dim3 grid(unsigned(tiles_s * tiles_c), unsigned(no));
     Timed timed(g, GBR_K_SWEEP_XI + D);
     if (D == 0)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, true, R>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, R>), grid, dim3(kBlock), 0, g->stream, a);
+    else if (!fuse_rk)
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, R>), grid, dim3(kBlock), 0, g->stream, a);
     else
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, false, R>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, R>), grid, dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }
 
+// One RHS: primitives of Q (unless given), cell gradients and sensor, the
+// sweeps; with fuse_rk the last sweep applies the SSP-RK3 stage.
 template <int NDIM, bool VISC, class R>
-hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a)
+hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool fuse_rk = false)
 {
     unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
     hipError_t e;
-    {
+    if (prims) {
         Timed timed(g, GBR_K_PRIMS);
         hipLaunchKernelGGL((k_prims<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     }
@@ -514,8 +590,8 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a)
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = sweep<0, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
-    if ((e = sweep<1, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
-    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R>(g, a);
+    if ((e = sweep<1, NDIM, VISC, R>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
+    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R>(g, a, fuse_rk);
     return e;
 }
 
@@ -535,6 +611,11 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;
     a.flags = g->flags;
+    a.Qw = nullptr;
+    a.Qn = nullptr;
+    a.dt = nullptr;
+    a.ca = a.cb = 0.0;
+    a.prim_out = nullptr;
     return a;
 }
 
@@ -548,11 +629,34 @@ hipError_t rhs_typed(gbr_grid_s *g, const double *Q, R *res)
     return visc ? rhs_all<2, true, R>(g, a) : rhs_all<2, false, R>(g, a);
 }
 
+static const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
+
+// One gbr_step stage: stage 0 forms the primitives of Q into the first
+// primitive buffer; each stage reads the buffer of its index parity and the
+// fused last sweep writes the next stage's primitives into the other one.
+template <class R>
+hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q)
+{
+    RhsArgs<R> a = make_args<R>(g, Q, static_cast<R *>(static_cast<void *>(g->res)));
+    R *buf[2] = {reinterpret_cast<R *>(g->prim), reinterpret_cast<R *>(g->prim2)};
+    a.prim = buf[stage % 2];
+    a.prim_out = stage < 2 ? buf[(stage + 1) % 2] : nullptr;
+    a.Qw = Q;
+    a.Qn = Qn;
+    a.dt = dt;
+    a.ca = kRkA[stage];
+    a.cb = kRkB[stage];
+    const bool visc = g->cfg.viscous != 0, first = stage == 0;
+    if (g->cfg.ndim == 3)
+        return visc ? rhs_all<3, true, R>(g, a, first, true) : rhs_all<3, false, R>(g, a, first, true);
+    return visc ? rhs_all<2, true, R>(g, a, first, true) : rhs_all<2, false, R>(g, a, first, true);
+}
+
 template <class R>
 hipError_t rk_typed(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q, const R *res)
 {
-    static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
-    static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double *A = kRkA, *B = kRkB;
     dim3 grid(unsigned((g->ncell + kBlock - 1) / kBlock));
     const double *jac = g->metrics + (long)GBR_SLOT_CELL_J * g->ncell;
     const double *ijt = g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell;
@@ -572,6 +676,12 @@ hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res)
 {
     if (g->cfg.precision == GBR_FP32_BULK) return rhs_typed<float>(g, Q, static_cast<float *>(res));
     return rhs_typed<double>(g, Q, static_cast<double *>(res));
+}
+
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q)
+{
+    if (g->cfg.precision == GBR_FP32_BULK) return step_stage_typed<float>(g, stage, dt, Qn, Q);
+    return step_stage_typed<double>(g, stage, dt, Qn, Q);
 }
 
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
