@@ -154,15 +154,22 @@ class Scheduler:
         return done
 
 
-def run(trace, executor, budget_bytes, tick_steps=TICK_STEPS, clock=time.perf_counter, sleep=time.sleep):
+def run(trace, executor, budget_bytes, tick_steps=TICK_STEPS, clock=time.perf_counter, sleep=time.sleep,
+        log=None, log_every=20.0):
     """Serve ``trace`` in real time (arrival times relative to the start) and
-    drain it. Returns a summary dict."""
+    drain it. Returns a summary dict. ``log`` (a callable taking a string)
+    receives a progress line every ``log_every`` seconds."""
     sched = Scheduler(budget_bytes, executor.bytes_of, tick_steps)
     pending = sorted(trace, key=lambda r: r.arrival)
     t0 = clock()
     ticks = 0
+    last_log = 0.0
     while pending or sched.queue or sched.active:
         now = clock() - t0
+        if log is not None and now - last_log >= log_every:
+            last_log = now
+            log(f"[serve] t={now:.1f}s done={len(sched.finished)}/{len(trace)} active={len(sched.active)} "
+                f"queued={len(sched.queue)} pending={len(pending)} used={sched.used / 2**30:.1f}GiB")
         while pending and pending[0].arrival <= now:
             sched.arrive(pending.pop(0))
         for r in sched.admit(now):
@@ -347,6 +354,7 @@ class GpuExecutor:
 def main(argv=None):
     import argparse
     import json
+    import sys
 
     import torch
 
@@ -366,13 +374,16 @@ def main(argv=None):
     ex = GpuExecutor()
     out = {"budget_bytes": budget, "trace": {"requests": a.requests, "rate_per_s": a.rate,
                                              "n2d": a.n2d, "n3d": a.n3d, "steps": a.steps}}
-    out["burst"] = run(trace, ex, budget)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+    out["burst"] = run(trace, ex, budget, log=log)
     print(json.dumps(out["burst"]), flush=True)
     if a.paced:
         cap = out["burst"]["achieved_cell_updates_per_s"]
         offered = out["burst"]["offered_cell_updates_per_s"]
         factor = 0.8 * cap / offered
-        out["paced"] = run(rescale(trace, factor), ex, budget)
+        out["paced"] = run(rescale(trace, factor), ex, budget, log=log)
         out["paced"]["rate_per_s"] = a.rate * factor
     ex.close()
     print(json.dumps(out), flush=True)
