@@ -60,6 +60,7 @@ class _Cfg(C.Structure):
         ("viscous", C.c_int),
         ("limiter", C.c_int),
         ("moving", C.c_int),
+        ("scheme", C.c_int),
         ("off", C.c_double * 9),
         ("gamma", C.c_double),
         ("Pr", C.c_double),
@@ -75,7 +76,8 @@ class _Cfg(C.Structure):
 
 DEFAULTS = dict(gamma=1.4, Pr=0.71, Re=1e4, Mref=1.0, suth=110.4 / 293.0,
                 viscous=False, limiter="mp", theta_c=0.5, alpha_mp=4.0, beta_mp=4.0,
-                alpha_d=4.0)
+                alpha_d=4.0, scheme="meg6")
+SCHEMES = {"meg6": 0, "mig4": 1}
 
 _lib = None
 _P = C.POINTER(C.c_double)
@@ -104,6 +106,9 @@ def lib():
         L.ref_step.restype = C.c_int
         for nm in ("ref_line_e6", "ref_line_hermite", "ref_line_face", "ref_line_dcomp"):
             getattr(L, nm).argtypes = [_P, C.c_int, C.c_double, _P]
+        for nm in ("ref_line_ig4", "ref_line_ig4_face", "ref_line_ig4_dcomp"):
+            getattr(L, nm).argtypes = [_P, C.c_int, C.c_double, _P]
+            getattr(L, nm).restype = C.c_int
         L.ref_eigvec.argtypes = [_P, C.c_double, C.c_double, _P, _P]
         L.ref_mp_limit.argtypes = [C.c_double] * 9
         L.ref_mp_limit.restype = C.c_double
@@ -132,6 +137,7 @@ def make_cfg(grid, **params):
     c.viscous = int(bool(p["viscous"]))
     c.limiter = LIM[p["limiter"]] if isinstance(p["limiter"], str) else int(p["limiter"])
     c.moving = int(grid.get("xyz_t") is not None)
+    c.scheme = SCHEMES[p["scheme"]] if isinstance(p["scheme"], str) else int(p["scheme"])
     off = np.asarray(grid["off"], dtype=np.float64).reshape(9)
     for q in range(9):
         c.off[q] = float(off[q])
@@ -245,6 +251,29 @@ def line_face(v, shift=0.0):
 
 def line_dcomp(v, shift=0.0):
     return _line("ref_line_dcomp", v, shift)
+
+
+def _line_checked(fn, v, shift):
+    v = _f64(v)
+    out = np.zeros_like(v)
+    if getattr(lib(), fn)(_ptr(v), len(v), float(shift), _ptr(out)) != 0:
+        raise FloatingPointError(f"{fn}: singular line system")
+    return out
+
+
+def line_ig4(v, shift=0.0):
+    """IG4 derivative (MIG4, Eq. IG4_grads) of a periodic line, v[i+n] = v[i] + shift."""
+    return _line_checked("ref_line_ig4", v, shift)
+
+
+def line_ig4_face(v, shift=0.0):
+    """Interface values at i + 1/2 built on IG4 gradients (Eq. FP-interp)."""
+    return _line_checked("ref_line_ig4_face", v, shift)
+
+
+def line_ig4_dcomp(v, shift=0.0):
+    """Difference of the IG4 interface values (Eq. FP-interp2)."""
+    return _line_checked("ref_line_ig4_dcomp", v, shift)
 
 
 def eigvec(nrm, rho, a):

@@ -156,6 +156,196 @@ void ref_line_dcomp(const double *v, int n, double shift, double *out)
 /* Metrics (Sec. 4, Sec. 7)                                                 */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* IG4 gradients of the MIG4 scheme (Eq. IG4_grads), read as differences as */
+/* Eq. E6_grads is, with alpha = 5/14:                                      */
+/*   alpha f'_{k-1} + f'_k + alpha f'_{k+1}                                  */
+/*     = a (f_{k+1} - f_{k-1}) + b (f_{k+2} - f_{k-2}),                     */
+/*   a = 2 (2 + alpha) / 6,  b = (4 alpha - 1) / 12.                         */
+/* On a periodic line the system is cyclic. A line whose periodic extension */
+/* satisfies F_{k+n} = F_k + J_k with J periodic (a coordinate, J = its     */
+/* period offset, or a coordinate times a periodic factor) has a derivative */
+/* whose extension satisfies F'_{k+n} = F'_k + (IG4 J)_k; the two rows that */
+/* reach across the ends carry that jump on their right-hand side. Each     */
+/* system is solved densely (Gaussian elimination with partial pivoting),   */
+/* which is slow and plain; lines are short in every use here.              */
+/* Pins: Fourier symbol of the scheme, linear-plus-periodic lines, fourth   */
+/* order, MIG4 metric identities and freestream.                            */
+/* ------------------------------------------------------------------------ */
+static const double ig4_alpha = 5.0 / 14.0;
+#define IG4_A (2.0 * (2.0 + ig4_alpha) / 6.0)
+#define IG4_B ((4.0 * ig4_alpha - 1.0) / 12.0)
+
+static int floor_div(int a, int n)
+{
+    int r = a % n;
+    if (r < 0) r += n;
+    return (a - r) / n;
+}
+
+static int mod_n(int a, int n)
+{
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Solve A y = r, A n x n row-major; A and r are overwritten. */
+static int solve_dense(double *A, double *r, int n, double *y)
+{
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int k = c + 1; k < n; ++k)
+            if (fabs(A[k * n + c]) > fabs(A[piv * n + c])) piv = k;
+        if (A[piv * n + c] == 0.0) return 1;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) {
+                double t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t;
+            }
+            double t = r[c]; r[c] = r[piv]; r[piv] = t;
+        }
+        for (int k = c + 1; k < n; ++k) {
+            double f = A[k * n + c] / A[c * n + c];
+            if (f == 0.0) continue;
+            for (int q = c; q < n; ++q) A[k * n + q] -= f * A[c * n + q];
+            r[k] -= f * r[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double s = r[c];
+        for (int q = c + 1; q < n; ++q) s -= A[c * n + q] * y[q];
+        y[c] = s / A[c * n + c];
+    }
+    return 0;
+}
+
+/* F_ext(m) of a line with jump J (J == NULL: periodic). */
+static double ext_val(const double *F, const double *J, int n, int m)
+{
+    int r = mod_n(m, n);
+    return J ? F[r] + (double)floor_div(m, n) * J[r] : F[r];
+}
+
+/* IG4 derivative y[0..n-1] of the line F with jump J; dj[0..n-1] (may be
+ * NULL) receives the jump of the derivative, IG4 of J. */
+static int ig4_ext(const double *F, const double *J, int n, double *y, double *dj)
+{
+    double *A = (double *)calloc((size_t)n * n, sizeof(double));
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *djl = (double *)calloc((size_t)n, sizeof(double));
+    int rc = (!A || !r || !djl) ? -1 : 0;
+    if (!rc && J) rc = ig4_ext(J, NULL, n, djl, NULL);
+    if (!rc) {
+        for (int k = 0; k < n; ++k) {
+            r[k] = IG4_A * (ext_val(F, J, n, k + 1) - ext_val(F, J, n, k - 1))
+                 + IG4_B * (ext_val(F, J, n, k + 2) - ext_val(F, J, n, k - 2));
+            A[k * n + k] += 1.0;
+            for (int s = -1; s <= 1; s += 2) {
+                int m = k + s, col = mod_n(m, n);
+                A[k * n + col] += ig4_alpha;
+                /* y_m = y_col + floor(m / n) * dj_col */
+                r[k] -= ig4_alpha * (double)floor_div(m, n) * djl[col];
+            }
+        }
+        rc = solve_dense(A, r, n, y);
+    }
+    if (!rc && dj) memcpy(dj, djl, sizeof(double) * n);
+    free(A); free(r); free(djl);
+    return rc;
+}
+
+/* Interface values I_{k+1/2}, k = -1 .. n-1 (face[k + 1]), of the line F
+ * with jump J: the average of the unlimited left and right states of
+ * Eq. vanleer-poly built on IG4 first derivatives and the Hermite second
+ * derivative (Eq. FP-interp). */
+static int ig4_faces(const double *F, const double *J, int n, double *face)
+{
+    double *y = (double *)malloc(sizeof(double) * n);
+    double *dj = (double *)malloc(sizeof(double) * n);
+    int rc = (!y || !dj) ? -1 : ig4_ext(F, J, n, y, dj);
+    if (!rc) {
+        for (int k = -1; k <= n - 1; ++k) {
+            double v[4], g[4];  /* cells k-1 .. k+2 */
+            for (int q = 0; q < 4; ++q) {
+                int m = k - 1 + q;
+                v[q] = ext_val(F, J, n, m);
+                g[q] = y[mod_n(m, n)] + (J ? (double)floor_div(m, n) * dj[mod_n(m, n)] : 0.0);
+            }
+            double hl = hermite(v + 1, g + 1);
+            double hr = hermite(v + 2, g + 2);
+            double left = v[1] + 0.5 * g[1] + hl / 12.0;
+            double right = v[2] - 0.5 * g[2] + hr / 12.0;
+            face[k + 1] = 0.5 * (left + right);
+        }
+    }
+    free(y); free(dj);
+    return rc;
+}
+
+int ref_line_ig4(const double *v, int n, double shift, double *out)
+{
+    double *J = (double *)malloc(sizeof(double) * n);
+    if (!J) return -1;
+    for (int i = 0; i < n; ++i) J[i] = shift;
+    int rc = ig4_ext(v, J, n, out, NULL);
+    free(J);
+    return rc;
+}
+
+int ref_line_ig4_face(const double *v, int n, double shift, double *out)
+{
+    double *J = (double *)calloc((size_t)n, sizeof(double));
+    double *f = (double *)malloc(sizeof(double) * (n + 1));
+    int rc = (!J || !f) ? -1 : 0;
+    if (!rc) {
+        for (int i = 0; i < n; ++i) J[i] = shift;
+        rc = ig4_faces(v, J, n, f);
+        if (!rc) for (int i = 0; i < n; ++i) out[i] = f[i + 1];
+    }
+    free(J); free(f);
+    return rc;
+}
+
+int ref_line_ig4_dcomp(const double *v, int n, double shift, double *out)
+{
+    double *J = (double *)calloc((size_t)n, sizeof(double));
+    double *f = (double *)malloc(sizeof(double) * (n + 1));
+    int rc = (!J || !f) ? -1 : 0;
+    if (!rc) {
+        for (int i = 0; i < n; ++i) J[i] = shift;
+        rc = ig4_faces(v, J, n, f);
+        if (!rc) for (int i = 0; i < n; ++i) out[i] = f[i + 1] - f[i];
+    }
+    free(J); free(f);
+    return rc;
+}
+
+/* Cells of the line along d through ijk, in order k = 0 .. n_d - 1. */
+static void line_cells(const ref_cfg *g, const int ijk[3], int d, long *cells)
+{
+    int t[3] = {ijk[0], ijk[1], ijk[2]};
+    for (int k = 0; k < g->n[d]; ++k) {
+        t[d] = k;
+        cells[k] = cell_index(g, t);
+    }
+}
+
+/* Visit every line along d: calls fn(ctx, cells) once per line. */
+static int for_lines(const ref_cfg *g, int d, int (*fn)(void *, const long *), void *ctx)
+{
+    long *cells = (long *)malloc(sizeof(long) * g->n[d]);
+    if (!cells) return -1;
+    int a = (d + 1) % 3, b = (d + 2) % 3, rc = 0;
+    for (int ib = 0; ib < g->n[b] && !rc; ++ib)
+        for (int ia = 0; ia < g->n[a] && !rc; ++ia) {
+            int ijk[3];
+            ijk[d] = 0; ijk[a] = ia; ijk[b] = ib;
+            line_cells(g, ijk, d, cells);
+            rc = fn(ctx, cells);
+        }
+    free(cells);
+    return rc;
+}
+
 /* Coordinate c of the periodic extension at neighbour m along d of a cell. */
 static double coord_ext(const ref_cfg *g, const double *xyz, const int ijk[3], int d, int m, int c)
 {
@@ -176,8 +366,11 @@ static void field_window(const ref_cfg *g, const double *f, const int ijk[3], in
  * metrics (Sec. 4.2) and the GCL rate (Eq. Jacb2).
  * Pins: composite stencil and 3-D identity coefficients (Sec. 7), discrete
  * metric identities, freestream on static and deforming grids.            */
+static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m);
+
 int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
 {
+    if (g->scheme == REF_SCHEME_MIG4) return metrics_mig4(g, xyz, xyz_t, m);
     const long N = ncell_of(g);
     double *dx = (double *)malloc(sizeof(double) * 9 * N); /* dx[(d*3+c)*N] = D_d of coord c */
     if (!dx) return -1;
@@ -288,6 +481,137 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
         }
         m[REF_M_INVJT * N + idx] = -s;
     }
+    return bad ? 1 : 0;
+}
+
+/* MIG4 metrics: the formulae and steps of ref_metrics (Eq. GCL_metrics,
+ * Jac-matrix, Jacb2) with D_d = difference of interface values built on IG4
+ * gradients (Eq. FP-interp, FP-interp2 with Eq. IG4_grads, as the paper
+ * directs for MIG4), and the interface values of the metrics from the same
+ * IG4 interpolation. The IG4 system couples a whole line, so lines are
+ * processed whole, in the coordinates as given.
+ * Pins: discrete metric identities, freestream, convergence of the metrics. */
+typedef struct {
+    const ref_cfg *g;
+    int d;              /* line direction                                  */
+    const double *fac;  /* per-cell factor (NULL: 1)                       */
+    const double *xc;   /* coordinate array (derivative jobs)              */
+    double jump;        /* coordinate shift per wrap along d               */
+    const double *src;  /* periodic field (interpolation jobs)             */
+    double *out;        /* per-cell result                                 */
+    int faces;          /* 0: D_d of fac * x, 1: interface values of src   */
+} line_job;
+
+static int line_job_fn(void *ctx, const long *cells)
+{
+    line_job *jb = (line_job *)ctx;
+    const int n = jb->g->n[jb->d];
+    double *F = (double *)calloc((size_t)n, sizeof(double));
+    double *J = (double *)calloc((size_t)n, sizeof(double));
+    double *f = (double *)malloc(sizeof(double) * (n + 1));
+    int rc = (!F || !J || !f) ? -1 : 0;
+    if (!rc) {
+        for (int k = 0; k < n; ++k) {
+            if (jb->faces) {
+                F[k] = jb->src[cells[k]];
+            } else {
+                double a = jb->fac ? jb->fac[cells[k]] : 1.0;
+                F[k] = a * jb->xc[cells[k]];
+                J[k] = a * jb->jump;
+            }
+        }
+        rc = ig4_faces(F, jb->faces ? NULL : J, n, f);
+        if (!rc)
+            for (int k = 0; k < n; ++k) jb->out[cells[k]] = jb->faces ? f[k + 1] : f[k + 1] - f[k];
+    }
+    free(F); free(J); free(f);
+    return rc;
+}
+
+static int run_job(line_job jb) { return for_lines(jb.g, jb.d, line_job_fn, &jb); }
+
+static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
+{
+    const long N = ncell_of(g);
+    double *dx = (double *)malloc(sizeof(double) * 9 * N);
+    double *ta = (double *)malloc(sizeof(double) * N);
+    double *tb = (double *)malloc(sizeof(double) * N);
+    int rc = (!dx || !ta || !tb) ? -1 : 0;
+    /* Step 1: coordinate derivatives D_d(x_c). */
+    for (int d = 0; d < 3 && !rc; ++d)
+        for (int c = 0; c < 3 && !rc; ++c) {
+            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0};
+            rc = run_job(jb);
+        }
+    /* Step 2: hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2]; the product
+     * shifts by (c1)_d1 * off[d2][c2] when the d2 index wraps.            */
+    for (int d = 0; d < 3 && !rc; ++d) {
+        int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int c = 0; c < 3 && !rc; ++c) {
+            int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0};
+            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0};
+            rc = run_job(ja);
+            if (!rc) rc = run_job(jc);
+            if (!rc)
+                for (long idx = 0; idx < N; ++idx) m[REF_M_HAT(d, c) * N + idx] = ta[idx] - tb[idx];
+        }
+    }
+    int bad = 0;
+    if (!rc) {
+        /* Step 3: 1/J = det[D_d x_c]; unhatted d_c = J hat(d)_c. */
+        for (long idx = 0; idx < N; ++idx) {
+            const double *a = dx + idx;
+#define DX(d, c) a[((d) * 3 + (c)) * N]
+            double invj = DX(0, 0) * (DX(1, 1) * DX(2, 2) - DX(1, 2) * DX(2, 1))
+                        - DX(0, 1) * (DX(1, 0) * DX(2, 2) - DX(1, 2) * DX(2, 0))
+                        + DX(0, 2) * (DX(1, 0) * DX(2, 1) - DX(1, 1) * DX(2, 0));
+#undef DX
+            if (!(invj > 0.0)) bad = 1;
+            m[REF_M_INVJ * N + idx] = invj;
+            m[REF_M_J * N + idx] = 1.0 / invj;
+            for (int d = 0; d < 3; ++d)
+                for (int c = 0; c < 3; ++c)
+                    m[REF_M_UNHAT(d, c) * N + idx] = m[REF_M_HAT(d, c) * N + idx] / invj;
+        }
+        /* Step 4: temporal metrics on moving grids. */
+        for (long idx = 0; idx < N; ++idx)
+            for (int d = 0; d < 3; ++d) {
+                double ht = 0.0;
+                if (g->moving && xyz_t)
+                    ht = -(xyz_t[idx] * m[REF_M_HAT(d, 0) * N + idx]
+                           + xyz_t[N + idx] * m[REF_M_HAT(d, 1) * N + idx]
+                           + xyz_t[2 * N + idx] * m[REF_M_HAT(d, 2) * N + idx]);
+                m[REF_M_HATT(d) * N + idx] = ht;
+                m[REF_M_UNHATT(d) * N + idx] = ht * m[REF_M_J * N + idx];
+            }
+    }
+    /* Step 5: interface values per family f with the IG4 interpolation. */
+    for (int f = 0; f < 3 && !rc; ++f) {
+        int src[13], dst[13], q = 0;
+        for (int c = 0; c < 3; ++c) { src[q] = REF_M_HAT(f, c); dst[q++] = REF_M_FHAT(f, c); }
+        src[q] = REF_M_HATT(f); dst[q++] = REF_M_FHATT(f);
+        for (int e = 0; e < 3; ++e)
+            for (int c = 0; c < 3; ++c) { src[q] = REF_M_UNHAT(e, c); dst[q++] = REF_M_FUNHAT(f, e, c); }
+        for (q = 0; q < 13 && !rc; ++q) {
+            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1};
+            rc = run_job(jb);
+        }
+    }
+    /* Step 6: GCL rate. */
+    if (!rc)
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            double sum = 0.0;
+            for (int f = 0; f < 3; ++f) {
+                const double *ft = m + REF_M_FHATT(f) * N;
+                sum += ft[idx] - ft[neighbour(g, ijk, f, -1, NULL)];
+            }
+            m[REF_M_INVJT * N + idx] = -sum;
+        }
+    free(dx); free(ta); free(tb);
+    if (rc) return -1;
     return bad ? 1 : 0;
 }
 
@@ -517,9 +841,67 @@ void ref_hllc(const double PL[5], const double PR[5], const double nt_n[4], doub
 /* Cell gradients (Step-1, Sec. 5.1; reused by Sec. 5.2 and the sensor).    */
 /* grad[(d * 4 + s) * N + cell], s = u, v, w, T; E6 along d.                */
 /* ------------------------------------------------------------------------ */
+/* IG4 derivative along d of a periodic cell field, every line. */
+typedef struct { const ref_cfg *g; int d; const double *src; double *out; } grad_job;
+
+static int grad_job_fn(void *ctx, const long *cells)
+{
+    grad_job *jb = (grad_job *)ctx;
+    const int n = jb->g->n[jb->d];
+    double *F = (double *)calloc((size_t)n, sizeof(double));
+    double *y = (double *)malloc(sizeof(double) * n);
+    int rc = (!F || !y) ? -1 : 0;
+    if (!rc) {
+        for (int k = 0; k < n; ++k) F[k] = jb->src[cells[k]];
+        rc = ig4_ext(F, NULL, n, y, NULL);
+        if (!rc) for (int k = 0; k < n; ++k) jb->out[cells[k]] = y[k];
+    }
+    free(F); free(y);
+    return rc;
+}
+
+/* Primitive fields (rho, u, v, w, p, T), 6 * N. */
+static void primitive_fields(const ref_cfg *g, const double *Q, double *pr)
+{
+    const long N = ncell_of(g);
+    for (long idx = 0; idx < N; ++idx) {
+        prim_t s = primitive(g, Q, idx);
+        pr[idx] = s.r; pr[N + idx] = s.u; pr[2 * N + idx] = s.v;
+        pr[3 * N + idx] = s.w; pr[4 * N + idx] = s.p; pr[5 * N + idx] = s.T;
+    }
+}
+
+/* MIG4: IG4 derivatives of all six primitive fields along every direction,
+ * pg[(d * 6 + s) * N], s = rho, u, v, w, p, T. */
+static int ig4_prim_grads(const ref_cfg *g, const double *Q, double *pg)
+{
+    const long N = ncell_of(g);
+    double *pr = (double *)malloc(sizeof(double) * 6 * N);
+    if (!pr) return -1;
+    primitive_fields(g, Q, pr);
+    int rc = 0;
+    for (int d = 0; d < 3 && !rc; ++d)
+        for (int q = 0; q < 6 && !rc; ++q) {
+            grad_job jb = {g, d, pr + q * N, pg + (d * 6 + q) * N};
+            rc = for_lines(g, d, grad_job_fn, &jb);
+        }
+    free(pr);
+    return rc;
+}
+
 void ref_gradients(const ref_cfg *g, const double *Q, double *grad)
 {
     const long N = ncell_of(g);
+    if (g->scheme == REF_SCHEME_MIG4) {
+        /* (u, v, w, T) gradients from the IG4 primitive gradients */
+        double *pg = (double *)malloc(sizeof(double) * 18 * N);
+        if (pg && !ig4_prim_grads(g, Q, pg))
+            for (int d = 0; d < 3; ++d)
+                for (int s = 0; s < 4; ++s)
+                    memcpy(grad + (d * 4 + s) * N, pg + (d * 6 + s + 1) * N, sizeof(double) * N);
+        free(pg);
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; ++idx) {
         int ijk[3];
@@ -565,7 +947,8 @@ void ref_sensor(const ref_cfg *g, const double *m, const double *grad, double *t
 /* neighbour: Steps 1-6 of Sec. 5.1 and Steps 1-4 of Sec. 5.2.             */
 /* ------------------------------------------------------------------------ */
 static int face_flux(const ref_cfg *g, const double *m, const double *Q, const double *grad,
-                     const double *theta, int f, const int ijk[3], long idx, double phi[5])
+                     const double *pgrad, const double *theta, int f, const int ijk[3], long idx,
+                     double phi[5])
 {
     const long N = ncell_of(g);
     /* primitives on the line, offsets -5 .. +6 about cell i */
@@ -577,10 +960,15 @@ static int face_flux(const ref_cfg *g, const double *m, const double *Q, const d
         P[q + 5][0] = s.r; P[q + 5][1] = s.u; P[q + 5][2] = s.v; P[q + 5][3] = s.w; P[q + 5][4] = s.p;
         T[q + 5] = s.T;
     }
-    /* Step-1: E6 first derivatives at offsets -2..3, Hermite second at -1..2 */
+    /* Step-1: first derivatives at offsets -2..3 (E6 for MEG6; the IG4 line
+     * derivatives for MIG4), Hermite second derivatives at -1..2 */
     double D1[6][5], D2[4][5];
     for (int q = -2; q <= 3; ++q)
         for (int s = 0; s < 5; ++s) {
+            if (pgrad) {
+                D1[q + 2][s] = pgrad[(f * 6 + s) * N + nb[q + 5]];
+                continue;
+            }
             double w[7];
             for (int t = -3; t <= 3; ++t) w[t + 3] = P[q + t + 5][s];
             D1[q + 2][s] = e6(w + 3);
@@ -650,6 +1038,10 @@ static int face_flux(const ref_cfg *g, const double *m, const double *Q, const d
         /* Sec. 5.2, Step-1: interface gradients of (u, v, w, T). */
         double dT[2], wT[7];
         for (int q = 0; q <= 1; ++q) {
+            if (pgrad) {
+                dT[q] = pgrad[(f * 6 + 5) * N + nb[q + 5]];
+                continue;
+            }
             for (int t = -3; t <= 3; ++t) wT[t + 3] = T[q + t + 5];
             dT[q] = e6(wT + 3);
         }
@@ -720,8 +1112,13 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
     double *grad = (double *)calloc((size_t)12 * N, sizeof(double));
     double *theta = (double *)calloc((size_t)N, sizeof(double));
     double *phi = (double *)malloc(sizeof(double) * 5 * N);
+    double *pgrad = NULL;
     if (!grad || !theta || !phi) { free(grad); free(theta); free(phi); return -1; }
     ref_gradients(g, Q, grad);
+    if (g->scheme == REF_SCHEME_MIG4) {
+        pgrad = (double *)malloc(sizeof(double) * 18 * N);
+        if (!pgrad || ig4_prim_grads(g, Q, pgrad)) { free(grad); free(theta); free(phi); free(pgrad); return -1; }
+    }
     if (g->limiter == REF_LIM_DUCROS) ref_sensor(g, m, grad, theta);
     int bad = 0;
     for (long idx = 0; idx < N; ++idx) {
@@ -735,7 +1132,7 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
             int ijk[3];
             double ph[5];
             unpack(g, idx, ijk);
-            if (face_flux(g, m, Q, grad, theta, f, ijk, idx, ph)) bad = 1;
+            if (face_flux(g, m, Q, grad, pgrad, theta, f, ijk, idx, ph)) bad = 1;
             for (int s = 0; s < 5; ++s) phi[s * N + idx] = ph[s];
         }
 #pragma omp parallel for schedule(static)
@@ -752,6 +1149,7 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
     free(grad);
     free(theta);
     free(phi);
+    free(pgrad);
     return bad ? 1 : 0;
 }
 

@@ -22,6 +22,7 @@ extern "C" {
 #endif
 
 enum { REF_LIM_NONE = 0, REF_LIM_MP = 1, REF_LIM_DUCROS = 2 };
+enum { REF_SCHEME_MEG6 = 0, REF_SCHEME_MIG4 = 1 };
 enum { REF_DT_CFL = 0, REF_DT_FIXED = 1 };
 
 typedef struct {
@@ -30,6 +31,7 @@ typedef struct {
     int viscous;       /* 0: Euler, 1: Navier-Stokes (alpha-damping)         */
     int limiter;       /* REF_LIM_*                                          */
     int moving;        /* 1: grid velocities given, GCL terms active         */
+    int scheme;        /* REF_SCHEME_MEG6 (E6 gradients) or REF_SCHEME_MIG4 (IG4) */
     double off[3][3];  /* periodic coordinate shift per wrapped direction   */
     double gamma, Pr, Re, Mref, suth; /* suth = Sutherland S / T_ref        */
     double theta_c;    /* shock-sensor threshold                             */
@@ -58,6 +60,13 @@ void ref_line_e6(const double *v, int n, double shift, double *out);
 void ref_line_hermite(const double *v, int n, double shift, double *out);
 void ref_line_face(const double *v, int n, double shift, double *out);
 void ref_line_dcomp(const double *v, int n, double shift, double *out);
+/* IG4 (Eq. IG4_grads) on a periodic line with v[i+n] = v[i] + shift; out[i]
+ * = derivative. ref_line_ig4_face: interface values at i + 1/2 (Eq. FP-interp
+ * with IG4 gradients); ref_line_ig4_dcomp: their difference (Eq. FP-interp2).
+ * Return nonzero if the line system is singular.                           */
+int ref_line_ig4(const double *v, int n, double shift, double *out);
+int ref_line_ig4_face(const double *v, int n, double shift, double *out);
+int ref_line_ig4_dcomp(const double *v, int n, double shift, double *out);
 
 /* --- pointwise pieces --------------------------------------------------- */
 void ref_eigvec(const double nrm[3], double rho, double a, double R[25], double Rinv[25]);
