@@ -893,12 +893,14 @@ void ref_gradients(const ref_cfg *g, const double *Q, double *grad)
 {
     const long N = ncell_of(g);
     if (g->scheme == REF_SCHEME_MIG4) {
-        /* (u, v, w, T) gradients from the IG4 primitive gradients */
+        /* (u, v, w, T) gradients from the IG4 primitive gradients, whose
+         * fields are ordered (rho, u, v, w, p, T) */
+        static const int from[4] = {1, 2, 3, 5};
         double *pg = (double *)malloc(sizeof(double) * 18 * N);
         if (pg && !ig4_prim_grads(g, Q, pg))
             for (int d = 0; d < 3; ++d)
                 for (int s = 0; s < 4; ++s)
-                    memcpy(grad + (d * 4 + s) * N, pg + (d * 6 + s + 1) * N, sizeof(double) * N);
+                    memcpy(grad + (d * 4 + s) * N, pg + (d * 6 + from[s]) * N, sizeof(double) * N);
         free(pg);
         return;
     }

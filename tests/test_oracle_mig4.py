@@ -153,3 +153,21 @@ def test_mig4_differs_from_meg6_on_rough_data():
     r6 = oracle.rhs(g, oracle.metrics(g), Q)
     r4 = oracle.rhs(g, oracle.metrics(g, scheme="mig4"), Q, scheme="mig4")
     assert np.abs(r6 - r4).max() > 1e-3 * np.abs(r6).max()
+
+
+def test_mig4_cell_gradients_are_ig4_of_each_field():
+    """The MIG4 cell gradients (viscous tangential terms, sensor) in slot
+    (d, s), s = u, v, w, T, equal the IG4 line derivative of that field along
+    d (T = gamma Mref^2 p / rho, Sec. 2)."""
+    g = W.random3d((7, 6, 5), seed=8)
+    Q = W.random_rough_state(g, seed=3, amp=0.2)
+    Mref = 0.7
+    grad = oracle.gradients(g, Q, scheme="mig4", Mref=Mref)
+    rho, u, v, w, p = oracle.prim_from_Q(Q)
+    T = 1.4 * Mref * Mref * p / rho
+    fields = [u, v, w, T]
+    for d in range(3):
+        axis = 2 - d
+        for s, f in enumerate(fields):
+            want = np.apply_along_axis(oracle.line_ig4, axis, f)
+            assert np.abs(grad[d * 4 + s] - want).max() <= 1e-13 * max(1.0, np.abs(want).max()), (d, s)
