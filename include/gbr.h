@@ -54,6 +54,12 @@ enum { GBR_LIM_NONE = 0, GBR_LIM_MP = 1, GBR_LIM_DUCROS = 2 };
  * viscous flux and Res in float.                                            */
 enum { GBR_FP64 = 0, GBR_FP32_BULK = 1 };
 enum { GBR_DT_CFL = 0, GBR_DT_FIXED = 1 };
+/* Gradient scheme of Sec. 5.1 Step-1: GBR_SCHEME_MEG6 uses the explicit
+ * sixth-order gradients (Eq. E6_grads), GBR_SCHEME_MIG4 the fourth-order
+ * implicit gradients (Eq. IG4_grads, alpha = 5/14), in the reconstruction,
+ * the viscous gradients, the sensor and, as Sec. 7 directs, the metric
+ * interpolation.                                                           */
+enum { GBR_SCHEME_MEG6 = 0, GBR_SCHEME_MIG4 = 1 };
 
 typedef struct gbr_config {
     int32_t ndim;      /* 2 or 3 (n[2] must be 1 when ndim == 2)                  */
@@ -63,6 +69,7 @@ typedef struct gbr_config {
                        /* paper, App. E), or MP where a Ducros sensor flags       */
     int32_t moving;    /* 1: grid velocities are supplied, GCL terms (Sec. 4.2)   */
     int32_t precision; /* GBR_FP64 or GBR_FP32_BULK                               */
+    int32_t scheme;    /* GBR_SCHEME_MEG6 or GBR_SCHEME_MIG4                      */
     double off[3][3];  /* periodic coordinate shift per wrapped direction         */
     double gamma;      /* ratio of specific heats (1.4 in the paper)              */
     double Pr;         /* Prandtl number (0.71)                                   */
@@ -97,7 +104,7 @@ typedef struct gbr_grid_s *gbr_grid;
  * size given by gbr_grid_bytes) and binds hip_stream (a hipStream_t, or NULL
  * for the default stream). Metrics are undefined until gbr_metrics.
  * Errors: GBR_E_ARG (null pointer, ndim not 2/3, n < 1, n[2] != 1 in 2-D,
- * unknown limiter or precision, non-positive gamma/Re/Pr/Mref),
+ * unknown limiter, precision or scheme, non-positive gamma/Re/Pr/Mref),
  * GBR_E_NOMEM, GBR_E_DEVICE. *out is NULL on error.                        */
 gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *out);
 
@@ -203,8 +210,8 @@ typedef struct gbr_batch_s *gbr_batch;
 enum { GBR_TILE_AUTO = -1, GBR_TILE_16X16 = 0, GBR_TILE_32X8 = 1, GBR_TILE_8X32 = 2, GBR_TILE_COUNT = 3 };
 
 /* Bind n >= 1 grids and their states for batched stepping.
- * Every grid must be 2-D, inviscid, static, with limiter GBR_LIM_NONE or
- * GBR_LIM_MP, and all must share precision, limiter, gamma, the MP
+ * Every grid must be 2-D, inviscid, static, MEG6, with limiter GBR_LIM_NONE
+ * or GBR_LIM_MP, and all must share precision, limiter, gamma, the MP
  * constants, the stream and the device; a grid may appear once. Metrics
  * must be computed (gbr_metrics) before gbr_batch_run.
  * Q[b]: device state of grid b, advanced in place by gbr_batch_run; it must

@@ -84,6 +84,7 @@ bool config_ok(const gbr_config *c, const char **why)
         return *why = "grid larger than 2^31 cells", false;
     if (c->limiter < GBR_LIM_NONE || c->limiter > GBR_LIM_DUCROS) return *why = "unknown limiter", false;
     if (c->precision != GBR_FP64 && c->precision != GBR_FP32_BULK) return *why = "unsupported precision", false;
+    if (c->scheme != GBR_SCHEME_MEG6 && c->scheme != GBR_SCHEME_MIG4) return *why = "unknown scheme", false;
     if (!(c->gamma > 1.0) || !(c->Re > 0.0) || !(c->Pr > 0.0) || !(c->Mref > 0.0) || !(c->suth >= 0.0))
         return *why = "gamma must exceed 1 and Re, Pr, Mref be positive", false;
     return true;
@@ -93,7 +94,8 @@ size_t bytes_for(const gbr_config *c)
 {
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     size_t nv = (size_t)c->ndim + 2;
-    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 12 + 2 * nv) + 1 + gbr::kReducePartials;
+    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 12 + 2 * nv + (c->scheme == GBR_SCHEME_MIG4 ? 6 : 0)) + 1 +
+                     gbr::kReducePartials;
     return doubles * sizeof(double) + sizeof(unsigned long long) + 2 * sizeof(int);
 }
 
@@ -128,7 +130,8 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->prim, (void *)g->prim2,
+    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->grad2, (void *)g->prim,
+                    (void *)g->prim2,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
@@ -175,6 +178,7 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     alloc((void **)&g->metrics, N * GBR_SLOT_COUNT * sizeof(double));
     alloc((void **)&g->scratch, N * 12 * sizeof(double));
     alloc((void **)&g->theta, N * sizeof(double));
+    if (cfg->scheme == GBR_SCHEME_MIG4) alloc((void **)&g->grad2, N * 6 * sizeof(double));
     alloc((void **)&g->prim, N * 6 * sizeof(double));
     alloc((void **)&g->prim2, N * 6 * sizeof(double));
     alloc((void **)&g->partial, gbr::kReducePartials * sizeof(double));

@@ -18,6 +18,7 @@ struct gbr_grid_s {
     double *metrics = nullptr;   // GBR_SLOT_COUNT * ncell
     double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
     double *theta = nullptr;     // ncell: shock sensor
+    double *grad2 = nullptr;     // 6 * ncell, MIG4 only: IG4 gradients of rho and p, (d * 2 + s)
     double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
     double *prim2 = nullptr;     // 6 * ncell: second primitive buffer (gbr_step stages alternate)
     double *partial = nullptr;   // kReducePartials: per-block minima of the time-step reduction
@@ -56,6 +57,20 @@ struct Phys {
     double alpha_mp, beta_mp, alpha_d;
     int limiter;
 };
+
+// Wide explicit stencils of the MIG4 gradient and of the metric derivative
+// and interface interpolation built on it (gbr_stencil.hip).
+constexpr int kIg4Half = 48;
+constexpr int kIg4DHalf = kIg4Half + 2;
+struct Ig4Stencil {
+    double w[kIg4Half + 1];  // f'_i = sum_{j = 1..kIg4Half} w[j] (f_{i+j} - f_{i-j})
+};
+struct Ig4MetricStencil {
+    double d[kIg4DHalf + 1];     // D f_i = sum_{j = 1..kIg4DHalf} d[j] (f_{i+j} - f_{i-j})
+    double e[2 * kIg4Half + 4];  // I_{i+1/2} = sum_{m = -(H+1)..H+2} e[m + H + 1] f_{i+m}, H = kIg4Half
+};
+const Ig4Stencil &ig4_stencil();
+const Ig4MetricStencil &ig4_metric_stencil();
 
 Dims dims_of(const gbr_grid_s *g);
 Phys phys_of(const gbr_grid_s *g);

@@ -59,7 +59,40 @@ __device__ __forceinline__ double coord(const MetricArgs &a, int c, long nb)
     return a.xyz[c * a.dm.ncell + nb];
 }
 
-__global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
+// Composite central derivative (Eq. FP-interp2) at the window centre of the
+// extended values f(q), q = offset along the line: the closed 11-point form
+// for MEG6, the wide IG4-based stencil for MIG4 (Sec. 7).
+template <bool IG4, class F>
+__device__ __forceinline__ double composite(const Ig4MetricStencil &s, F f)
+{
+    if (IG4) {
+        double acc = 0.0;
+        for (int j = 1; j <= kIg4DHalf; ++j) acc += s.d[j] * (f(j) - f(-j));
+        return acc;
+    }
+    double v[11];
+#pragma unroll
+    for (int q = -5; q <= 5; ++q) v[q + 5] = f(q);
+    return dcomp(v + 5);
+}
+
+// Interface value at +1/2 (Eq. FP-interp / interp-formulae) of f(q).
+template <bool IG4, class F>
+__device__ __forceinline__ double interface(const Ig4MetricStencil &s, F f)
+{
+    if (IG4) {
+        double acc = 0.0;
+        for (int m = -(kIg4Half + 1); m <= kIg4Half + 2; ++m) acc += s.e[m + kIg4Half + 1] * f(m);
+        return acc;
+    }
+    double v[10];
+#pragma unroll
+    for (int q = -4; q <= 5; ++q) v[q + 4] = f(q);
+    return face_interp(v + 4);
+}
+
+template <bool IG4>
+__global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricStencil st)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     if (idx >= a.dm.ncell) return;
@@ -69,45 +102,42 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a)
     // translation invariant and this avoids cancellation of O(|x| / dx).
     // The periodic image (x + wraps * offset) is formed first, then shifted,
     // so a window across the seam rounds like one that does not cross it.
-    double v[11];
     for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 3; ++c) {
             const double org = coord(a, c, idx);
-            for (int q = -5; q <= 5; ++q) {
+            a.dx[(d * 3 + c) * a.dm.ncell + idx] = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d, q, &wr);
-                v[q + 5] = (coord(a, c, nb) + wr * a.off[d][c]) - org;
-            }
-            a.dx[(d * 3 + c) * a.dm.ncell + idx] = dcomp(v + 5);
+                return (coord(a, c, nb) + wr * a.off[d][c]) - org;
+            });
         }
 }
 
-__global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a)
+template <bool IG4>
+__global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a, Ig4MetricStencil st)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     if (idx >= a.dm.ncell) return;
     const long N = a.dm.ncell;
     int ijk[3];
     unpack(a.dm, idx, ijk);
-    double v[11];
     double hat[3][3];
     for (int d = 0; d < 3; ++d) {
         const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3; ++c) {
             const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
             const double org = coord(a, c2, idx);
-            for (int q = -5; q <= 5; ++q) {
+            double ta = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d2, q, &wr);
-                v[q + 5] = a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d2][c2]) - org);
-            }
-            double ta = dcomp(v + 5);
-            for (int q = -5; q <= 5; ++q) {
+                return a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d2][c2]) - org);
+            });
+            double tb = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d1, q, &wr);
-                v[q + 5] = a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d1][c2]) - org);
-            }
-            hat[d][c] = ta - dcomp(v + 5);
+                return a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d1][c2]) - org);
+            });
+            hat[d][c] = ta - tb;
         }
     }
     double x[3][3];
@@ -136,22 +166,22 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a)
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a)
+template <bool IG4>
+__global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4MetricStencil st)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     if (idx >= a.dm.ncell) return;
     const long N = a.dm.ncell;
     int ijk[3];
     unpack(a.dm, idx, ijk);
-    long nb[10];
-    double v[10];
     double *m = a.m;
     for (int f = 0; f < 3; ++f) {
-        for (int q = -4; q <= 5; ++q) nb[q + 4] = step_to(a.dm, ijk, f, q, nullptr);
+        long nb[10];  // MEG6 window, reused by every slot
+        if (!IG4)
+            for (int q = -4; q <= 5; ++q) nb[q + 4] = step_to(a.dm, ijk, f, q, nullptr);
         auto interp = [&](int slot) {
             const double *s = m + slot * N;
-            for (int q = 0; q < 10; ++q) v[q] = s[nb[q]];
-            return face_interp(v + 4);
+            return interface<IG4>(st, [&](int q) { return IG4 ? s[step_to(a.dm, ijk, f, q, nullptr)] : s[nb[q + 4]]; });
         };
         for (int c = 0; c < 3; ++c) m[GBR_SLOT_FACE_HAT(f, c) * N + idx] = interp(GBR_SLOT_CELL_HAT(f, c));
         m[GBR_SLOT_FACE_HATT(f) * N + idx] = interp(GBR_SLOT_CELL_HATT(f));
@@ -198,9 +228,18 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
     a.flags = g->flags;
     unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
     Timed timed(g, GBR_K_METRICS);
-    hipLaunchKernelGGL(k_coord_deriv, dim3(blocks), dim3(kBlock), 0, g->stream, a);
-    hipLaunchKernelGGL(k_cell_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);
-    hipLaunchKernelGGL(k_face_metrics, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    const Ig4MetricStencil &st = ig4_metric_stencil();
+    if (g->cfg.scheme == GBR_SCHEME_MIG4) {
+        hipLaunchKernelGGL(k_coord_deriv<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+        hipLaunchKernelGGL(k_cell_metrics<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+    } else {
+        hipLaunchKernelGGL(k_coord_deriv<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+        hipLaunchKernelGGL(k_cell_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+    }
+    if (g->cfg.scheme == GBR_SCHEME_MIG4)
+        hipLaunchKernelGGL(k_face_metrics<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+    else
+        hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
     hipLaunchKernelGGL(k_gcl, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }

@@ -51,6 +51,7 @@ struct RhsArgs {
     const double *Q;
     R *res;
     R *grad;       // 12 * ncell: (d * 4 + s), s = u, v, w, T
+    R *grad2;      // 6 * ncell (MIG4): (d * 2 + s), s = rho, p
     R *theta;      // ncell
     R *prim;       // 6 * ncell: rho, u, v, w, p, T
     const double *m;  // metrics (always double)
@@ -92,6 +93,77 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
     a.prim[5 * N + idx] = R(T);
     if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)))
         atomicOr(a.flags, 1);
+}
+
+// Ducros sensor (builder-defined gate of the limiter): theta = div^2 /
+// (div^2 + |curl|^2 + 1e-30) of the physical velocity gradient
+// G[a][b] = sum_d (d_{x_b}) du_a/dd from the computational gradients gd[d][a].
+template <class R>
+__device__ __forceinline__ R ducros_theta(const R gd[3][4], const double *m, long N, long idx)
+{
+    R G[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        R mb[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) mb[d] = R(m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx]);
+#pragma unroll
+        for (int aa = 0; aa < 3; ++aa) G[aa][b] = mb[0] * gd[0][aa] + mb[1] * gd[1][aa] + mb[2] * gd[2][aa];
+    }
+    R div = G[0][0] + G[1][1] + G[2][2];
+    R wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
+    R d2 = div * div;
+    return d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
+}
+
+// MIG4 gradients (Eq. IG4_grads) along direction D of the six primitives,
+// one thread per cell, with the explicit wide stencil equal to the implicit
+// scheme (gbr_stencil.hip): f'_i = sum_j w_j (f_{i+j} - f_{i-j}), periodic.
+template <int D, int NDIM, class R>
+__global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    const long N = a.dm.ncell;
+    if (idx >= N) return;
+    int ijk[3];
+    ijk[0] = int(idx % a.dm.n[0]);
+    ijk[1] = int((idx / a.dm.n[0]) % a.dm.n[1]);
+    ijk[2] = int(idx / ((long)a.dm.n[0] * a.dm.n[1]));
+    const int n = a.dm.n[D], k = ijk[D];
+    const long stride = (D == 0) ? 1 : (D == 1) ? a.dm.n[0] : (long)a.dm.n[0] * a.dm.n[1];
+    const long base = idx - (long)k * stride;
+    R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    for (int j = 1; j <= kIg4Half; ++j) {
+        const long cp = base + (long)wrap_index(k + j, n) * stride;
+        const long cm = base + (long)wrap_index(k - j, n) * stride;
+        const R w = R(st.w[j]);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            if (NDIM == 2 && v == 3) continue;
+            acc[v] += w * (a.prim[v * N + cp] - a.prim[v * N + cm]);
+        }
+    }
+    a.grad2[(D * 2 + 0) * N + idx] = acc[0];
+    a.grad[(D * 4 + 0) * N + idx] = acc[1];
+    a.grad[(D * 4 + 1) * N + idx] = acc[2];
+    a.grad[(D * 4 + 2) * N + idx] = acc[3];
+    a.grad[(D * 4 + 3) * N + idx] = acc[5];
+    a.grad2[(D * 2 + 1) * N + idx] = acc[4];
+}
+
+// Sensor from the stored cell gradients (MIG4).
+template <int NDIM, class R>
+__global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    const long N = a.dm.ncell;
+    if (idx >= N) return;
+    R gd[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gd[d][q] = (d < NDIM) ? a.grad[(d * 4 + q) * N + idx] : R(0);
+    a.theta[idx] = ducros_theta(gd, a.m, N, idx);
 }
 
 // Gradient tile: GI x GJ cells in the (i, j) plane, marching KC planes along
@@ -154,23 +226,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
-            if (SENSOR) {
-                // physical velocity gradient G[a][b] = sum_d (d_{x_b}) du_a/dd
-                R G[3][3];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    R mb[3];
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) mb[d] = R(a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx]);
-#pragma unroll
-                    for (int aa = 0; aa < 3; ++aa)
-                        G[aa][b] = mb[0] * gd[0][aa] + mb[1] * gd[1][aa] + mb[2] * gd[2][aa];
-                }
-                R div = G[0][0] + G[1][1] + G[2][2];
-                R wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
-                R d2 = div * div;
-                a.theta[idx] = d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
-            }
+            if (SENSOR) a.theta[idx] = ducros_theta(gd, a.m, N, idx);
         }
         __syncthreads();
         if (NDIM == 3) {
@@ -222,7 +278,7 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
 #endif
 // MODE: 0 writes Res, 1 adds to Res, 2 adds to Res and applies the SSP-RK3
 // stage to the tile's own cells (the last sweep of a gbr_step stage).
-template <int D, int NDIM, bool VISC, int MODE, class R>
+template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R>
 __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
 {
     using T = Tile<D>;
@@ -256,16 +312,26 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
         for (int v = 0; v < 5; ++v) sP[v * VP + at] = a.prim[v * N + c];
     }
     __syncthreads();
-    // Phase 2: E6 first derivatives of cells s0-3 .. s0+TS+1
+    // Phase 2: first derivatives of cells s0-3 .. s0+TS+1: E6 from the LDS
+    // pencils (MEG6), or the stored IG4 gradients (MIG4)
     for (int e = tid; e < V1; e += kBlock) {
         int sl = (D == 0) ? e % N1 : e / TC;
         int cl = (D == 0) ? e / N1 : e % TC;
-        int pc = T::at(sl + 3, cl, NP);
         int at = T::at(sl, cl, N1);
+        if (IG4) {
+            const long c = cell_of(dm, T::SD, T::CD, wrap_index(s0 - 3 + sl, ns), min(c0 + cl, nc - 1), o);
+            s1[0 * V1 + at] = a.grad2[(D * 2 + 0) * N + c];
+            s1[1 * V1 + at] = a.grad[(D * 4 + 0) * N + c];
+            s1[2 * V1 + at] = a.grad[(D * 4 + 1) * N + c];
+            s1[3 * V1 + at] = a.grad[(D * 4 + 2) * N + c];
+            s1[4 * V1 + at] = a.grad2[(D * 2 + 1) * N + c];
+        } else {
+            int pc = T::at(sl + 3, cl, NP);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const R *x = sP + v * VP + pc;
-            s1[v * V1 + at] = e6(x[-3 * st], x[-2 * st], x[-st], x[st], x[2 * st], x[3 * st]);
+            for (int v = 0; v < 5; ++v) {
+                const R *x = sP + v * VP + pc;
+                s1[v * V1 + at] = e6(x[-3 * st], x[-2 * st], x[-st], x[st], x[2 * st], x[3 * st]);
+            }
         }
     }
     __syncthreads();
@@ -549,7 +615,7 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
     if (e < n) d[e] = s[e];
 }
 
-template <int D, int NDIM, bool VISC, class R>
+template <int D, int NDIM, bool VISC, class R, bool IG4>
 hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
 {
     using T = Tile<D>;
@@ -559,11 +625,11 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
     dim3 grid(unsigned(tiles_s * tiles_c), unsigned(no));
     Timed timed(g, GBR_K_SWEEP_XI + D);
     if (D == 0)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, R>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
     else if (!fuse_rk)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, R>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
     else
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, R>), grid, dim3(kBlock), 0, g->stream, a);
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }
 
@@ -578,6 +644,26 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
         Timed timed(g, GBR_K_PRIMS);
         hipLaunchKernelGGL((k_prims<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     }
+    if (g->cfg.scheme == GBR_SCHEME_MIG4) {
+        // IG4 gradients of all primitives along every direction (they feed the
+        // reconstruction as well), then the sensor from them
+        {
+            Timed timed(g, GBR_K_CELL_GRAD);
+            const Ig4Stencil &st = ig4_stencil();
+            hipLaunchKernelGGL((k_ig4_grad<0, NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+            hipLaunchKernelGGL((k_ig4_grad<1, NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+            if (NDIM == 3)
+                hipLaunchKernelGGL((k_ig4_grad<NDIM == 3 ? 2 : 1, NDIM, R>), dim3(blocks), dim3(kBlock), 0,
+                                   g->stream, a, st);
+            if (a.pr.limiter == GBR_LIM_DUCROS)
+                hipLaunchKernelGGL((k_sensor<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = sweep<0, NDIM, VISC, R, true>(g, a)) != hipSuccess) return e;
+        if ((e = sweep<1, NDIM, VISC, R, true>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
+        if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, true>(g, a, fuse_rk);
+        return e;
+    }
     // cell gradients feed only the tangential viscous terms and the sensor
     if (VISC || a.pr.limiter == GBR_LIM_DUCROS) {
         Timed timed(g, GBR_K_CELL_GRAD);
@@ -589,9 +675,9 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
             hipLaunchKernelGGL((k_cell_grad<NDIM, false, R>), gg, dim3(kBlock), 0, g->stream, a);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = sweep<0, NDIM, VISC, R>(g, a)) != hipSuccess) return e;
-    if ((e = sweep<1, NDIM, VISC, R>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
-    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R>(g, a, fuse_rk);
+    if ((e = sweep<0, NDIM, VISC, R, false>(g, a)) != hipSuccess) return e;
+    if ((e = sweep<1, NDIM, VISC, R, false>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
+    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, false>(g, a, fuse_rk);
     return e;
 }
 
@@ -607,6 +693,7 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.Q = Q;
     a.res = res;
     a.grad = reinterpret_cast<R *>(g->scratch);
+    a.grad2 = reinterpret_cast<R *>(g->grad2);
     a.theta = reinterpret_cast<R *>(g->theta);
     a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;

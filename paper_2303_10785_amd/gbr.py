@@ -20,6 +20,8 @@ STATUS_NAMES = {0: "GBR_OK", 1: "GBR_E_ARG", 2: "GBR_E_JACOBIAN", 3: "GBR_E_STAT
 LIM = {"none": 0, "mp": 1, "ducros": 2}
 GBR_FP64, GBR_FP32_BULK = 0, 1
 PRECISION = {"fp64": GBR_FP64, "fp32_bulk": GBR_FP32_BULK}
+GBR_SCHEME_MEG6, GBR_SCHEME_MIG4 = 0, 1
+SCHEME = {"meg6": GBR_SCHEME_MEG6, "mig4": GBR_SCHEME_MIG4}
 GBR_DT_CFL, GBR_DT_FIXED = 0, 1
 GBR_TILE_AUTO, GBR_TILE_16X16, GBR_TILE_32X8, GBR_TILE_8X32 = -1, 0, 1, 2
 TILE_NAMES = {0: "16x16", 1: "32x8", 2: "8x32"}
@@ -73,6 +75,7 @@ class gbr_config(C.Structure):
         ("limiter", C.c_int32),
         ("moving", C.c_int32),
         ("precision", C.c_int32),
+        ("scheme", C.c_int32),
         ("off", C.c_double * 9),
         ("gamma", C.c_double),
         ("Pr", C.c_double),
@@ -169,7 +172,7 @@ def _check(status, handle=None):
 
 def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1.4, Pr=0.71,
                 Re=1e4, Mref=1.0, suth=110.4 / 293.0, theta_c=0.5, alpha_mp=4.0, beta_mp=4.0,
-                alpha_d=4.0, precision="fp64"):
+                alpha_d=4.0, precision="fp64", scheme="meg6"):
     c = gbr_config()
     c.ndim = int(ndim)
     for d in range(3):
@@ -178,6 +181,7 @@ def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1
     c.limiter = LIM[limiter] if isinstance(limiter, str) else int(limiter)
     c.moving = int(bool(moving))
     c.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    c.scheme = SCHEME[scheme] if isinstance(scheme, str) else int(scheme)
     flat = [float(v) for row in off for v in row]
     for q in range(9):
         c.off[q] = flat[q]
