@@ -142,6 +142,39 @@ def fp32_bulk_leg(G64, grid, Q0, args, dev, ncell):
             "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in kern.items() if v[1]}}
 
 
+def mig4_leg(grid, Q0, args, dev, ncell):
+    """The same jet workload with the MIG4 scheme (IG4 gradients and
+    IG4-based metrics): step time and kernel breakdown."""
+    import torch
+
+    from paper_2303_10785_amd import gbr
+
+    G = gbr.Grid(grid, scheme="mig4", **PARAMS)
+    gbr.gbr_timing_enable(G.h, True)
+    G.metrics(torch.from_numpy(grid["xyz"]).to(dev))
+    metrics_ms = gbr.gbr_timing_collect(G.h)["metrics"][0]
+    Q = torch.from_numpy(Q0).to(dev)
+    dt = torch.zeros(1, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        G.step(Q, CFL, gbr.GBR_DT_CFL, dt_out=dt)
+    gbr.gbr_timing_collect(G.h)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        G.step(Q, CFL, gbr.GBR_DT_CFL, dt_out=dt)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / args.steps
+    kern = gbr.gbr_timing_collect(G.h)
+    state = G.check_state()
+    G.close()
+    log(f"bench mig4: {ms:.3f} ms/step, metrics {metrics_ms:.1f} ms")
+    return {"ms_per_step": ms, "value": ncell * 3 / (ms * 1e-3), "unit": "cell-updates/s", "dtype": "f64",
+            "metrics_ms": metrics_ms, "state_ok": state == gbr.GBR_OK,
+            "kernels_ms_per_launch": {k: v[0] / v[1] for k, v in kern.items() if v[1]}}
+
+
 BATCH_STEPS = 100
 BATCH_CFL = 0.4
 
@@ -319,6 +352,7 @@ def main():
     # FP32-bulk on the same workload: step time and the error of one RHS
     # against the FP64 path (which matches the oracle to 1e-12)
     fp32 = fp32_bulk_leg(G, grid, Q0, args, dev, ncell)
+    mig4 = mig4_leg(grid, Q0, args, dev, ncell)
 
     line = {
         "metric": "cell-updates/s per RHS at 13M cells (% HBM peak); batched solves/s + p99 latency",
@@ -340,6 +374,7 @@ def main():
         "roofline": roofline,
         "kernels": breakdown,
         "fp32_bulk": fp32,
+        "mig4": mig4,
         "paper_context": PAPER_CONTEXT,
     }
     G.close()

@@ -69,6 +69,17 @@ __device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
     return i + (long)dm.n[0] * (j + (long)dm.n[1] * k);
 }
 
+// Linear index of the cell at position s along direction sd, c along cd and
+// o along the remaining direction.
+__device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, int c, int o)
+{
+    int t[3];
+    t[sd] = s;
+    t[cd] = c;
+    t[3 - sd - cd] = o;
+    return pack(dm, t[0], t[1], t[2]);
+}
+
 // ----------------------------------------------------------------------------
 // primitives, cell gradients and sensor
 // ----------------------------------------------------------------------------
@@ -116,39 +127,65 @@ __device__ __forceinline__ R ducros_theta(const R gd[3][4], const double *m, lon
     return d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
 }
 
-// MIG4 gradients (Eq. IG4_grads) along direction D of the six primitives,
-// one thread per cell, with the explicit wide stencil equal to the implicit
-// scheme (gbr_stencil.hip): f'_i = sum_j w_j (f_{i+j} - f_{i-j}), periodic.
+// MIG4 gradients (Eq. IG4_grads) along direction D of the six primitives
+// with the explicit wide stencil that equals the implicit scheme
+// (gbr_stencil.hip): f'_i = sum_j w_j (f_{i+j} - f_{i-j}), periodic. A
+// workgroup stages a segment of IG4_TS cells along D (plus a halo of
+// kIg4Half cells on each side) for IG4_TC lines in LDS, one variable at a
+// time; along xi one line per workgroup, along eta / zeta 16 lines side by
+// side (i fastest, coalesced) with each thread owning 4 cells along D.
+template <int D>
+struct Ig4Tile {
+    static constexpr int TC = (D == 0) ? 1 : 16;
+    static constexpr int TS = (D == 0) ? 256 : 64;
+    static constexpr int SD = D;
+    static constexpr int CD = (D == 0) ? 1 : 0;
+    static constexpr int OD = (D == 2) ? 1 : 2;
+    static constexpr int LEN = TS + 2 * kIg4Half;
+};
+
 template <int D, int NDIM, class R>
 __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st)
 {
-    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
-    const long N = a.dm.ncell;
-    if (idx >= N) return;
-    int ijk[3];
-    ijk[0] = int(idx % a.dm.n[0]);
-    ijk[1] = int((idx / a.dm.n[0]) % a.dm.n[1]);
-    ijk[2] = int(idx / ((long)a.dm.n[0] * a.dm.n[1]));
-    const int n = a.dm.n[D], k = ijk[D];
-    const long stride = (D == 0) ? 1 : (D == 1) ? a.dm.n[0] : (long)a.dm.n[0] * a.dm.n[1];
-    const long base = idx - (long)k * stride;
-    R acc[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    for (int j = 1; j <= kIg4Half; ++j) {
-        const long cp = base + (long)wrap_index(k + j, n) * stride;
-        const long cm = base + (long)wrap_index(k - j, n) * stride;
-        const R w = R(st.w[j]);
-#pragma unroll
-        for (int v = 0; v < 6; ++v) {
-            if (NDIM == 2 && v == 3) continue;
-            acc[v] += w * (a.prim[v * N + cp] - a.prim[v * N + cm]);
+    using T = Ig4Tile<D>;
+    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN;
+    __shared__ R buf[LEN * TC];
+    const Dims &dm = a.dm;
+    const long N = dm.ncell;
+    const int ns = dm.n[T::SD], nc = dm.n[T::CD];
+    const int tiles_s = (ns + TS - 1) / TS;
+    const int s0 = (blockIdx.x % tiles_s) * TS;
+    const int c0 = (blockIdx.x / tiles_s) * TC;
+    const int o = blockIdx.y;
+    const int tid = threadIdx.x;
+    R *outs[6] = {a.grad2 + (D * 2 + 0) * N, a.grad + (D * 4 + 0) * N, a.grad + (D * 4 + 1) * N,
+                  a.grad + (D * 4 + 2) * N, a.grad2 + (D * 2 + 1) * N, a.grad + (D * 4 + 3) * N};
+    for (int v = 0; v < 6; ++v) {
+        if (NDIM == 2 && v == 3) {
+            // w is identically zero in 2-D
+            for (int q = tid; q < TS * TC; q += kBlock) {
+                const int sl = q / TC, cl = q % TC;
+                if (s0 + sl < ns && c0 + cl < nc) outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = R(0);
+            }
+            continue;
         }
+        const R *f = a.prim + (long)v * N;
+        for (int e = tid; e < LEN * TC; e += kBlock) {
+            const int sl = e / TC, cl = e % TC;
+            buf[e] = f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cl, nc - 1), o)];
+        }
+        __syncthreads();
+        for (int q = tid; q < TS * TC; q += kBlock) {
+            const int sl = q / TC, cl = q % TC;
+            if (s0 + sl < ns && c0 + cl < nc) {
+                const R *c = buf + (sl + H) * TC + cl;
+                R acc = R(0);
+                for (int j = 1; j <= H; ++j) acc += R(st.w[j]) * (c[j * TC] - c[-j * TC]);
+                outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = acc;
+            }
+        }
+        __syncthreads();
     }
-    a.grad2[(D * 2 + 0) * N + idx] = acc[0];
-    a.grad[(D * 4 + 0) * N + idx] = acc[1];
-    a.grad[(D * 4 + 1) * N + idx] = acc[2];
-    a.grad[(D * 4 + 2) * N + idx] = acc[3];
-    a.grad[(D * 4 + 3) * N + idx] = acc[5];
-    a.grad2[(D * 2 + 1) * N + idx] = acc[4];
 }
 
 // Sensor from the stored cell gradients (MIG4).
@@ -262,14 +299,6 @@ struct Tile {
     __device__ static constexpr int c_of(int tid) { return D == 0 ? tid / TS : tid % TC; }
 };
 
-__device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, int c, int o)
-{
-    int t[3];
-    t[sd] = s;
-    t[cd] = c;
-    t[3 - sd - cd] = o;
-    return pack(dm, t[0], t[1], t[2]);
-}
 
 #ifdef GBR_SWEEP_MINWAVES
 #define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock, GBR_SWEEP_MINWAVES)
@@ -633,6 +662,15 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
     return hipGetLastError();
 }
 
+template <int D, int NDIM, class R>
+void ig4_grad(gbr_grid_s *g, const RhsArgs<R> &a, const Ig4Stencil &st)
+{
+    using T = Ig4Tile<D>;
+    const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
+    dim3 grid(unsigned(((ns + T::TS - 1) / T::TS) * ((nc + T::TC - 1) / T::TC)), unsigned(no));
+    hipLaunchKernelGGL((k_ig4_grad<D, NDIM, R>), grid, dim3(kBlock), 0, g->stream, a, st);
+}
+
 // One RHS: primitives of Q (unless given), cell gradients and sensor, the
 // sweeps; with fuse_rk the last sweep applies the SSP-RK3 stage.
 template <int NDIM, bool VISC, class R>
@@ -650,11 +688,9 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
         {
             Timed timed(g, GBR_K_CELL_GRAD);
             const Ig4Stencil &st = ig4_stencil();
-            hipLaunchKernelGGL((k_ig4_grad<0, NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
-            hipLaunchKernelGGL((k_ig4_grad<1, NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
-            if (NDIM == 3)
-                hipLaunchKernelGGL((k_ig4_grad<NDIM == 3 ? 2 : 1, NDIM, R>), dim3(blocks), dim3(kBlock), 0,
-                                   g->stream, a, st);
+            ig4_grad<0, NDIM, R>(g, a, st);
+            ig4_grad<1, NDIM, R>(g, a, st);
+            if (NDIM == 3) ig4_grad<NDIM == 3 ? 2 : 1, NDIM, R>(g, a, st);
             if (a.pr.limiter == GBR_LIM_DUCROS)
                 hipLaunchKernelGGL((k_sensor<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
         }
