@@ -168,6 +168,22 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
  * update). Clears the flags.                                                */
 gbr_status gbr_check_state(gbr_grid g);
 
+/* Diagnostics from the cell gradients the scheme shares (Sec. 3 names
+ * vorticity, enstrophy, density-gradient magnitude and the Q-criterion as
+ * uses of them; Eq. KE-Ens defines the kinetic-energy and enstrophy
+ * averages). With G = du_a/dx_b from the scheme's cell gradients (E6 or
+ * IG4) and the unhatted cell metrics:
+ *   fields[b] (device, 5 * ncell doubles, may be NULL): vorticity x, y, z
+ *   (curl u), Q-criterion (|W|^2 - |S|^2) / 2 with S, W the symmetric and
+ *   antisymmetric parts of G, and |grad rho|;
+ *   integrals[b] (device, 3 doubles, may be NULL): volume averages of
+ *   rho |u|^2 / 2 and rho |curl u|^2 / 2, and the volume sum of 1/J.
+ * Cell volumes are 1/J; the sums are taken in a fixed order, so repeated
+ * calls give identical results. Uses the grid's gradient scratch (not
+ * concurrently with gbr_rhs / gbr_step on the same grid). Asynchronous.    */
+gbr_status gbr_diagnostics(const gbr_grid *g, int n, const double *const *Q, double *const *fields,
+                           double *const *integrals);
+
 /* Read-only device pointer to one metric slot (GBR_SLOT_*), ncell doubles,
  * owned by the library; NULL on a bad slot. Valid until gbr_grid_destroy.  */
 const double *gbr_metric_ptr(gbr_grid g, int slot);
@@ -183,7 +199,8 @@ enum {
     GBR_K_CFL = 6,         /* time-step reduction                                */
     GBR_K_COPY = 7,        /* state copies and fills                             */
     GBR_K_PRIMS = 8,       /* primitive variables of the state                   */
-    GBR_K_COUNT = 9
+    GBR_K_DIAG = 9,        /* diagnostics                                        */
+    GBR_K_COUNT = 10
 };
 
 /* Per-kernel timing for benchmarks: while enabled (on != 0), every kernel

@@ -110,6 +110,8 @@ def lib():
             getattr(L, nm).argtypes = [_P, C.c_int, C.c_double, _P]
             getattr(L, nm).restype = C.c_int
         L.ref_eigvec.argtypes = [_P, C.c_double, C.c_double, _P, _P]
+        L.ref_diagnostics.argtypes = [cfgp, _P, _P, _P, _P]
+        L.ref_diagnostics.restype = C.c_int
         L.ref_mp_limit.argtypes = [C.c_double] * 9
         L.ref_mp_limit.restype = C.c_double
         L.ref_hllc.argtypes = [_P, _P, _P, C.c_double, _P]
@@ -297,6 +299,17 @@ def euler_flux(P, nt_n, gamma=1.4):
     F = np.zeros(5)
     lib().ref_euler_flux(_ptr(_f64(P)), _ptr(_f64(nt_n)), float(gamma), _ptr(F))
     return F
+
+
+def diagnostics(grid, m, Q, **params):
+    """(fields[5] = vorticity x, y, z, Q-criterion, |grad rho|; (KE, enstrophy, volume))."""
+    cfg = make_cfg(grid, **params)
+    Q = _f64(Q)
+    f = np.zeros((5,) + _shape(grid))
+    it = np.zeros(3)
+    if lib().ref_diagnostics(C.byref(cfg), _ptr(_f64(m)), _ptr(Q), _ptr(f), _ptr(it)) != 0:
+        raise MemoryError("oracle diagnostics")
+    return f, tuple(it)
 
 
 def prim_from_Q(Q, gamma=1.4):

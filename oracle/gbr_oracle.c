@@ -1156,6 +1156,85 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Post-processing diagnostics from the shared gradients (Sec. 3 lists      */
+/* vorticity, enstrophy, density-gradient magnitude and the Q-criterion as  */
+/* uses of the cell gradients; Eq. KE-Ens defines the volume averages of    */
+/* rho |u|^2 / 2 and rho |Omega|^2 / 2). The physical velocity gradient is  */
+/* G[a][b] = sum_d (d_{x_b}) du_a/dd with the cell gradients of the scheme  */
+/* (E6 or IG4) and the unhatted cell metrics; Omega = curl u; Q = (|W|^2 -  */
+/* |S|^2) / 2 with S, W the symmetric and antisymmetric parts of G (the     */
+/* usual definition; the paper names it without a formula). Integrals are   */
+/* sums of cell values times the cell volume 1/J.                           */
+/* Pins: closed-form shear flows (vorticity, Q, integrals), exact volume    */
+/* and kinetic energy on affine grids, convergence on curvilinear grids.    */
+/* ------------------------------------------------------------------------ */
+int ref_diagnostics(const ref_cfg *g, const double *m, const double *Q, double *fields, double *integrals)
+{
+    const long N = ncell_of(g);
+    double *grad = (double *)calloc((size_t)12 * N, sizeof(double));
+    double *rgrad = (double *)calloc((size_t)3 * N, sizeof(double));
+    double *pr = (double *)malloc(sizeof(double) * 6 * N);
+    if (!grad || !rgrad || !pr) { free(grad); free(rgrad); free(pr); return -1; }
+    ref_gradients(g, Q, grad);
+    primitive_fields(g, Q, pr);
+    /* density gradients along each computational direction */
+    int rc = 0;
+    if (g->scheme == REF_SCHEME_MIG4) {
+        for (int d = 0; d < g->ndim && !rc; ++d) {
+            grad_job jb = {g, d, pr, rgrad + d * N};
+            rc = for_lines(g, d, grad_job_fn, &jb);
+        }
+    } else {
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            for (int d = 0; d < g->ndim; ++d) {
+                double w[7];
+                field_window(g, pr, ijk, d, -3, 3, w);
+                rgrad[d * N + idx] = e6(w + 3);
+            }
+        }
+    }
+    double ke = 0.0, ens = 0.0, vol = 0.0;
+    for (long idx = 0; idx < N && !rc; ++idx) {
+        double G[3][3], gr[3];
+        for (int b = 0; b < 3; ++b) {
+            for (int a = 0; a < 3; ++a) {
+                double s = 0.0;
+                for (int d = 0; d < g->ndim; ++d) s += m[REF_M_UNHAT(d, b) * N + idx] * grad[(d * 4 + a) * N + idx];
+                G[a][b] = s;
+            }
+            double s = 0.0;
+            for (int d = 0; d < g->ndim; ++d) s += m[REF_M_UNHAT(d, b) * N + idx] * rgrad[d * N + idx];
+            gr[b] = s;
+        }
+        double om[3] = {G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]};
+        double s2 = 0.0, w2 = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double sab = 0.5 * (G[a][b] + G[b][a]), wab = 0.5 * (G[a][b] - G[b][a]);
+                s2 += sab * sab;
+                w2 += wab * wab;
+            }
+        fields[0 * N + idx] = om[0];
+        fields[1 * N + idx] = om[1];
+        fields[2 * N + idx] = om[2];
+        fields[3 * N + idx] = 0.5 * (w2 - s2);
+        fields[4 * N + idx] = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+        double rho = pr[idx], u = pr[N + idx], v = pr[2 * N + idx], w = pr[3 * N + idx];
+        double dv = m[REF_M_INVJ * N + idx];
+        ke += 0.5 * rho * (u * u + v * v + w * w) * dv;
+        ens += 0.5 * rho * (om[0] * om[0] + om[1] * om[1] + om[2] * om[2]) * dv;
+        vol += dv;
+    }
+    integrals[0] = ke / vol;
+    integrals[1] = ens / vol;
+    integrals[2] = vol;
+    free(grad); free(rgrad); free(pr);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Time step (App. B) and SSP-RK3 stage (App. B with Eq. time-split).       */
 /* ------------------------------------------------------------------------ */
 double ref_cfl_min(const ref_cfg *g, const double *m, const double *Q)

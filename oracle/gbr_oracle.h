@@ -83,6 +83,11 @@ void ref_gradients(const ref_cfg *cfg, const double *Q, double *grad);
 void ref_sensor(const ref_cfg *cfg, const double *m, const double *grad, double *theta);
 int ref_rhs(const ref_cfg *cfg, const double *m, const double *Q, double *res);
 double ref_cfl_min(const ref_cfg *cfg, const double *m, const double *Q);
+/* Diagnostics from the shared cell gradients: fields[5][cells] = vorticity
+ * (x, y, z), Q-criterion, |grad rho|; integrals[3] = kinetic energy and
+ * enstrophy per unit volume (Eq. KE-Ens) and the volume sum of 1/J.
+ * Returns nonzero on allocation failure.                                  */
+int ref_diagnostics(const ref_cfg *cfg, const double *m, const double *Q, double *fields, double *integrals);
 void ref_rk_stage(const ref_cfg *cfg, const double *m, int stage, double dt,
                   const double *Qn, double *Q, const double *res);
 int ref_step(const ref_cfg *cfg, double *m, const double *xyz, const double *xyz_t,

@@ -320,6 +320,22 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
     return GBR_OK;
 }
 
+gbr_status gbr_diagnostics(const gbr_grid *g, int n, const double *const *Q, double *const *fields,
+                           double *const *integrals)
+{
+    gbr_status s = batch_ok(g, n);
+    if (s != GBR_OK) return s;
+    if (n == 0) return GBR_OK;
+    if (!Q) return fail(g[0], GBR_E_ARG, "null state array");
+    for (int b = 0; b < n; ++b) {
+        if (!Q[b]) return fail(g[b], GBR_E_ARG, "null state");
+        hipError_t e = gbr::launch_diagnostics(g[b], Q[b], fields ? fields[b] : nullptr,
+                                               integrals ? integrals[b] : nullptr);
+        if (e != hipSuccess) return hip_fail(g[b], e, "diagnostics launch");
+    }
+    return GBR_OK;
+}
+
 gbr_status gbr_check_state(gbr_grid g)
 {
     if (!g) return GBR_E_ARG;

@@ -95,6 +95,9 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
 hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res);
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
                            double *Q, const void *res);
+// Diagnostics from the shared cell gradients (fields may be null, integrals
+// may be null).
+hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, double *integrals);
 // RHS and SSP-RK3 stage of gbr_step with the stage fused into the last sweep.
 hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);

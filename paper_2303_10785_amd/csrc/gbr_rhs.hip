@@ -26,6 +26,8 @@
 // the sensor, the reconstruction, limiter, HLLC, viscous flux and Res in
 // float, while Q, the metrics, J and (1/J)_t stay in double and the RK stage
 // accumulates in double.
+#include <algorithm>
+
 #include "gbr_device.hpp"
 #include "gbr_internal.hpp"
 
@@ -662,6 +664,111 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// diagnostics from the shared cell gradients (vorticity, Q-criterion,
+// |grad rho|; kinetic-energy and enstrophy averages of Eq. KE-Ens)
+// ----------------------------------------------------------------------------
+constexpr int kDiagBlocks = 1024;
+
+template <int NDIM, bool IG4, class R>
+__global__ void __launch_bounds__(kBlock) k_diag(RhsArgs<R> a, double *fields, double *partial)
+{
+    const Dims &dm = a.dm;
+    const long N = dm.ncell;
+    double ke = 0.0, ens = 0.0, vol = 0.0;
+    for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
+        int ijk[3];
+        ijk[0] = int(idx % dm.n[0]);
+        ijk[1] = int((idx / dm.n[0]) % dm.n[1]);
+        ijk[2] = int(idx / ((long)dm.n[0] * dm.n[1]));
+        double gr[3], G[3][3];
+        double rd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+            if (IG4) {
+                rd[d] = double(a.grad2[(d * 2 + 0) * N + idx]);
+            } else {
+                // E6 derivative of rho along d (Eq. E6_grads)
+                const long stride = (d == 0) ? 1 : (d == 1) ? dm.n[0] : (long)dm.n[0] * dm.n[1];
+                const long base = idx - (long)ijk[d] * stride;
+                R f[7];
+#pragma unroll
+                for (int q = -3; q <= 3; ++q) f[q + 3] = a.prim[base + (long)wrap_index(ijk[d] + q, dm.n[d]) * stride];
+                rd[d] = double(e6(f[0], f[1], f[2], f[4], f[5], f[6]));
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            double mb[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) mb[d] = (d < NDIM) ? a.m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                double sum = 0.0;
+#pragma unroll
+                for (int d = 0; d < NDIM; ++d) sum += mb[d] * double(a.grad[(d * 4 + q) * N + idx]);
+                G[q][b] = sum;
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int d = 0; d < NDIM; ++d) sum += mb[d] * rd[d];
+            gr[b] = sum;
+        }
+        const double om[3] = {G[2][1] - G[1][2], G[0][2] - G[2][0], G[1][0] - G[0][1]};
+        double s2 = 0.0, w2 = 0.0;
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const double sab = 0.5 * (G[p][q] + G[q][p]), wab = 0.5 * (G[p][q] - G[q][p]);
+                s2 += sab * sab;
+                w2 += wab * wab;
+            }
+        if (fields) {
+            fields[idx] = om[0];
+            fields[N + idx] = om[1];
+            fields[2 * N + idx] = om[2];
+            fields[3 * N + idx] = 0.5 * (w2 - s2);
+            fields[4 * N + idx] = sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+        }
+        const double rho = double(a.prim[idx]), u = double(a.prim[N + idx]), v = double(a.prim[2 * N + idx]),
+                     w = double(a.prim[3 * N + idx]);
+        const double dv = a.m[GBR_SLOT_CELL_INVJ * N + idx];
+        ke += 0.5 * rho * (u * u + v * v + w * w) * dv;
+        ens += 0.5 * rho * (om[0] * om[0] + om[1] * om[1] + om[2] * om[2]) * dv;
+        vol += dv;
+    }
+    // block sums in a fixed order (wavefront shuffles, then the waves)
+    __shared__ double part[3][kBlock / 64];
+    double vals[3] = {ke, ens, vol};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double x = vals[q];
+        for (int off = warpSize / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (threadIdx.x % warpSize == 0) part[q][threadIdx.x / warpSize] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double x = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) x += part[threadIdx.x][w];
+        partial[threadIdx.x * kDiagBlocks + blockIdx.x] = x;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_diag_final(const double *partial, int nb, double *out)
+{
+    if (threadIdx.x != 0) return;
+    double t[3];
+    for (int q = 0; q < 3; ++q) {
+        double x = 0.0;
+        for (int b = 0; b < nb; ++b) x += partial[q * kDiagBlocks + b];
+        t[q] = x;
+    }
+    out[0] = t[0] / t[2];
+    out[1] = t[1] / t[2];
+    out[2] = t[2];
+}
+
 template <int D, int NDIM, class R>
 void ig4_grad(gbr_grid_s *g, const RhsArgs<R> &a, const Ig4Stencil &st)
 {
@@ -752,6 +859,53 @@ hipError_t rhs_typed(gbr_grid_s *g, const double *Q, R *res)
     return visc ? rhs_all<2, true, R>(g, a) : rhs_all<2, false, R>(g, a);
 }
 
+template <class R>
+hipError_t diag_typed(gbr_grid_s *g, const double *Q, double *fields, double *integrals)
+{
+    RhsArgs<R> a = make_args<R>(g, Q, nullptr);
+    const long N = g->ncell;
+    const unsigned blocks = unsigned((N + kBlock - 1) / kBlock);
+    const bool ig4 = g->cfg.scheme == GBR_SCHEME_MIG4;
+    Timed timed(g, GBR_K_DIAG);
+    const int nd = g->cfg.ndim;
+    if (nd == 3)
+        hipLaunchKernelGGL((k_prims<3, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    else
+        hipLaunchKernelGGL((k_prims<2, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    if (ig4) {
+        const Ig4Stencil &st = ig4_stencil();
+        if (nd == 3) {
+            ig4_grad<0, 3, R>(g, a, st);
+            ig4_grad<1, 3, R>(g, a, st);
+            ig4_grad<2, 3, R>(g, a, st);
+        } else {
+            ig4_grad<0, 2, R>(g, a, st);
+            ig4_grad<1, 2, R>(g, a, st);
+        }
+    } else {
+        dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
+                unsigned((a.dm.n[2] + KC - 1) / KC));
+        if (nd == 3)
+            hipLaunchKernelGGL((k_cell_grad<3, false, R>), gg, dim3(kBlock), 0, g->stream, a);
+        else
+            hipLaunchKernelGGL((k_cell_grad<2, false, R>), gg, dim3(kBlock), 0, g->stream, a);
+    }
+    const int nb = int(std::min<long>(kDiagBlocks, (N + kBlock - 1) / kBlock));
+    if (nd == 3) {
+        if (ig4)
+            hipLaunchKernelGGL((k_diag<3, true, R>), dim3(nb), dim3(kBlock), 0, g->stream, a, fields, g->partial);
+        else
+            hipLaunchKernelGGL((k_diag<3, false, R>), dim3(nb), dim3(kBlock), 0, g->stream, a, fields, g->partial);
+    } else {
+        if (ig4)
+            hipLaunchKernelGGL((k_diag<2, true, R>), dim3(nb), dim3(kBlock), 0, g->stream, a, fields, g->partial);
+        else
+            hipLaunchKernelGGL((k_diag<2, false, R>), dim3(nb), dim3(kBlock), 0, g->stream, a, fields, g->partial);
+    }
+    if (integrals) hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, g->stream, g->partial, nb, integrals);
+    return hipGetLastError();
+}
+
 static const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
 static const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 
@@ -799,6 +953,12 @@ hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res)
 {
     if (g->cfg.precision == GBR_FP32_BULK) return rhs_typed<float>(g, Q, static_cast<float *>(res));
     return rhs_typed<double>(g, Q, static_cast<double *>(res));
+}
+
+hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, double *integrals)
+{
+    if (g->cfg.precision == GBR_FP32_BULK) return diag_typed<float>(g, Q, fields, integrals);
+    return diag_typed<double>(g, Q, fields, integrals);
 }
 
 hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q)

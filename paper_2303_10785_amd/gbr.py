@@ -124,6 +124,8 @@ def lib():
     L.gbr_timing_collect.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     L.gbr_last_error.argtypes = [_VP]
     L.gbr_last_error.restype = C.c_char_p
+    L.gbr_diagnostics.argtypes = [_PP, C.c_int, _PP, _PP, _PP]
+    L.gbr_diagnostics.restype = C.c_int
     L.gbr_batch_create.argtypes = [_PP, C.c_int, _PP, C.c_int, C.POINTER(_VP)]
     L.gbr_batch_run.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.c_int]
     L.gbr_batch_query.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
@@ -251,7 +253,14 @@ def gbr_metric_ptr(h, slot):
 
 
 KERNEL_CLASSES = ["metrics", "cell_grad", "sweep_xi", "sweep_eta", "sweep_zeta", "rk_stage", "cfl", "copy",
-                  "prims"]
+                  "prims", "diagnostics"]
+
+
+def gbr_diagnostics(handles, Q, fields=None, integrals=None):
+    n = len(handles)
+    _check(lib().gbr_diagnostics(_arr(handles), n, _arr(Q), _arr(fields) if fields is not None else None,
+                                 _arr(integrals) if integrals is not None else None),
+           handles[0] if n else None)
 
 
 def gbr_timing_enable(h, on=True):
@@ -345,6 +354,12 @@ class Grid:
     def step(self, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None):
         gbr_step([self.h], [Q], cfl_or_dt, dt_mode, [xyz] if xyz is not None else None,
                  [xyz_t] if xyz_t is not None else None, [dt_out] if dt_out is not None else None)
+
+    def diagnostics(self, Q, fields=None, integrals=None):
+        """fields: device tensor [5][...] or None; integrals: device tensor of
+        3 doubles or None."""
+        gbr_diagnostics([self.h], [Q], [fields] if fields is not None else None,
+                        [integrals] if integrals is not None else None)
 
     def res_dtype(self):
         import torch

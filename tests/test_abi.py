@@ -72,6 +72,8 @@ def test_null_arguments_rejected_without_device_work():
     assert L.gbr_batch_run(None, 1, 0.4, 0, 1) == gbr.GBR_E_ARG
     assert L.gbr_batch_query(None, None, None, None) == gbr.GBR_E_ARG
     assert L.gbr_batch_destroy(None) == gbr.GBR_OK
+    assert L.gbr_diagnostics(None, 0, None, None, None) == gbr.GBR_OK
+    assert L.gbr_diagnostics(None, 1, None, None, None) == gbr.GBR_E_ARG
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
