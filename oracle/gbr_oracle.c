@@ -622,6 +622,8 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
  * where the cyclic pattern has xi; the cyclic form is used. Static grids. */
 static double c4(const double *v) { return (2.0 / 3.0) * (v[1] - v[-1]) - (1.0 / 12.0) * (v[2] - v[-2]); }
 
+/* Interface value at +1/2 with the fourth-order derivative: derivatives at
+ * the cells -1 .. 2 of the window reach two cells further, so v[-3 .. 4]. */
 static double face_central_c4(const double *v)
 {
     double gv[4], h[2];
@@ -675,18 +677,18 @@ int ref_metrics_nonfp(const ref_cfg *g, const double *xyz, double *m)
     free(dx);
     for (long idx = 0; idx < N; ++idx) {
         int ijk[3];
-        double w[6];
+        double w[8];
         unpack(g, idx, ijk);
         for (int f = 0; f < 3; ++f) {
             for (int c = 0; c < 3; ++c) {
-                field_window(g, m + REF_M_HAT(f, c) * N, ijk, f, -2, 3, w);
-                m[REF_M_FHAT(f, c) * N + idx] = face_central_c4(w + 2);
+                field_window(g, m + REF_M_HAT(f, c) * N, ijk, f, -3, 4, w);
+                m[REF_M_FHAT(f, c) * N + idx] = face_central_c4(w + 3);
             }
             m[REF_M_FHATT(f) * N + idx] = 0.0;
             for (int e = 0; e < 3; ++e)
                 for (int c = 0; c < 3; ++c) {
-                    field_window(g, m + REF_M_UNHAT(e, c) * N, ijk, f, -2, 3, w);
-                    m[REF_M_FUNHAT(f, e, c) * N + idx] = face_central_c4(w + 2);
+                    field_window(g, m + REF_M_UNHAT(e, c) * N, ijk, f, -3, 4, w);
+                    m[REF_M_FUNHAT(f, e, c) * N + idx] = face_central_c4(w + 3);
                 }
         }
     }
