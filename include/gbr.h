@@ -131,6 +131,16 @@ gbr_status gbr_set_stream(gbr_grid g, void *hip_stream);
 gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz,
                        const double *const *xyz_t);
 
+/* Negative control of App. D: non-freestream-preserving metrics in place
+ * of gbr_metrics, for static grids. Coordinate derivatives from the
+ * fourth-order central formula (Eq. 4thorder-grads), hat(d)_c =
+ * (c1)_d1 (c2)_d2 - (c1)_d2 (c2)_d1 (the cyclic form; the printed zeta_y
+ * entry has a zeta where the cycle has xi), interface values from
+ * Eq. interp-formulae with that derivative in place of E6. A uniform flow
+ * then does not stay uniform on curved grids (Sec. 8.1.1). Errors as
+ * gbr_metrics; GBR_E_UNSUPPORTED for moving grids.                         */
+gbr_status gbr_metrics_nonfp(const gbr_grid *g, int n, const double *const *xyz);
+
 /* Right-hand side Res = d(Q/J)/dt (Sec. 3, Sec. 5.1 Steps 1-7, Sec. 5.2
  * Steps 1-5): res[b] receives -sum_d [Phi(+1/2) - Phi(-1/2)] with
  * Phi = F - F^v, the directions accumulated in the order xi, eta, zeta.

@@ -240,6 +240,31 @@ gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz, const
     return GBR_OK;
 }
 
+gbr_status gbr_metrics_nonfp(const gbr_grid *g, int n, const double *const *xyz)
+{
+    gbr_status s = batch_ok(g, n);
+    if (s != GBR_OK) return s;
+    if (n == 0) return GBR_OK;
+    if (!xyz) return fail(g[0], GBR_E_ARG, "null coordinate array");
+    for (int b = 0; b < n; ++b) {
+        gbr_grid_s *gg = g[b];
+        if (!xyz[b]) return fail(gg, GBR_E_ARG, "null coordinates");
+        if (gg->cfg.moving) return fail(gg, GBR_E_UNSUPPORTED, "non-conservative metrics are for static grids");
+        hipError_t e = hipMemsetAsync(gg->flags + 1, 0, sizeof(int), gg->stream);
+        if (e == hipSuccess) e = gbr::launch_metrics_nonfp(gg, xyz[b]);
+        if (e != hipSuccess) return hip_fail(gg, e, "metrics launch");
+    }
+    for (int b = 0; b < n; ++b) {
+        gbr_grid_s *gg = g[b];
+        int flag = 0;
+        hipError_t e = hipMemcpyAsync(&flag, gg->flags + 1, sizeof(int), hipMemcpyDeviceToHost, gg->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(gg->stream);
+        if (e != hipSuccess) return hip_fail(gg, e, "metrics sync");
+        if (flag) return fail(gg, GBR_E_JACOBIAN, "non-positive Jacobian (folded or left-handed grid)");
+    }
+    return GBR_OK;
+}
+
 gbr_status gbr_rhs(const gbr_grid *g, int n, const double *const *Q, void *const *res)
 {
     gbr_status s = batch_ok(g, n);

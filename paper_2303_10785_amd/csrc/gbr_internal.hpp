@@ -92,6 +92,7 @@ class Timed {
 
 // Kernel launchers (enqueue on g->stream; return hipSuccess or the launch error).
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t);
+hipError_t launch_metrics_nonfp(gbr_grid_s *g, const double *xyz);
 hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res);
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
                            double *Q, const void *res);

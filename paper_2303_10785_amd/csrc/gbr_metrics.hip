@@ -206,6 +206,99 @@ __global__ void __launch_bounds__(kBlock) k_gcl(MetricArgs a)
     a.m[GBR_SLOT_CELL_INVJT * N + idx] = -s;
 }
 
+// --- App. D (non-freestream-preserving metrics, negative control) ---------
+// Fourth-order central derivative (Eq. 4thorder-grads) at the window centre.
+__device__ __forceinline__ double c4(const double *v)
+{
+    return (2.0 / 3.0) * (v[1] - v[-1]) - (1.0 / 12.0) * (v[2] - v[-2]);
+}
+
+// Interface value at +1/2 of v[-3..4]: Eq. interp-formulae with the
+// fourth-order derivative in place of E6 (derivatives at cells -1 .. 2, each
+// reaching two cells further).
+__device__ __forceinline__ double face_c4(const double *v)
+{
+    double gv[4];
+#pragma unroll
+    for (int q = -1; q <= 2; ++q) gv[q + 1] = c4(v + q);
+    const double h0 = 2.0 * (v[1] - 2.0 * v[0] + v[-1]) - 0.5 * (gv[2] - gv[0]);
+    const double h1 = 2.0 * (v[2] - 2.0 * v[1] + v[0]) - 0.5 * (gv[3] - gv[1]);
+    return 0.5 * ((v[0] + 0.5 * gv[1] + h0 / 12.0) + (v[1] - 0.5 * gv[2] + h1 / 12.0));
+}
+
+__global__ void __launch_bounds__(kBlock) k_coord_deriv_c4(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) {
+            double v[5];
+            for (int q = -2; q <= 2; ++q) {
+                int wr;
+                long nb = step_to(a.dm, ijk, d, q, &wr);
+                v[q + 2] = coord(a, c, nb) + wr * a.off[d][c];
+            }
+            a.dx[(d * 3 + c) * a.dm.ncell + idx] = c4(v + 2);
+        }
+}
+
+// hat(d)_c = (c1)_d1 (c2)_d2 - (c1)_d2 (c2)_d1 (App. D, cyclic form), J and
+// unhatted metrics; static grid.
+__global__ void __launch_bounds__(kBlock) k_cell_metrics_nonfp(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    const long N = a.dm.ncell;
+    double x[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) x[d][c] = a.dx[(d * 3 + c) * N + idx];
+    const double invj = x[0][0] * (x[1][1] * x[2][2] - x[1][2] * x[2][1]) -
+                        x[0][1] * (x[1][0] * x[2][2] - x[1][2] * x[2][0]) +
+                        x[0][2] * (x[1][0] * x[2][1] - x[1][1] * x[2][0]);
+    if (!(invj > 0.0)) atomicOr(a.flags + 1, 1);
+    double *m = a.m;
+    m[GBR_SLOT_CELL_INVJ * N + idx] = invj;
+    m[GBR_SLOT_CELL_J * N + idx] = 1.0 / invj;
+    m[GBR_SLOT_CELL_INVJT * N + idx] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int c = 0; c < 3; ++c) {
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            const double hat = x[d1][c1] * x[d2][c2] - x[d2][c1] * x[d1][c2];
+            m[GBR_SLOT_CELL_HAT(d, c) * N + idx] = hat;
+            m[GBR_SLOT_CELL_UNHAT(d, c) * N + idx] = hat / invj;
+        }
+        m[GBR_SLOT_CELL_HATT(d) * N + idx] = 0.0;
+        m[GBR_SLOT_CELL_UNHATT(d) * N + idx] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_face_metrics_c4(MetricArgs a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx >= a.dm.ncell) return;
+    const long N = a.dm.ncell;
+    int ijk[3];
+    unpack(a.dm, idx, ijk);
+    double *m = a.m;
+    for (int f = 0; f < 3; ++f) {
+        long nb[8];
+        for (int q = -3; q <= 4; ++q) nb[q + 3] = step_to(a.dm, ijk, f, q, nullptr);
+        auto interp = [&](int slot) {
+            double v[8];
+            for (int q = 0; q < 8; ++q) v[q] = m[slot * N + nb[q]];
+            return face_c4(v + 3);
+        };
+        for (int c = 0; c < 3; ++c) m[GBR_SLOT_FACE_HAT(f, c) * N + idx] = interp(GBR_SLOT_CELL_HAT(f, c));
+        m[GBR_SLOT_FACE_HATT(f) * N + idx] = 0.0;
+        for (int e = 0; e < 3; ++e)
+            for (int c = 0; c < 3; ++c)
+                m[GBR_SLOT_FACE_UNHAT(f, e, c) * N + idx] = interp(GBR_SLOT_CELL_UNHAT(e, c));
+    }
+}
+
 }  // namespace
 
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
@@ -241,6 +334,32 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
     else
         hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
     hipLaunchKernelGGL(k_gcl, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_metrics_nonfp(gbr_grid_s *g, const double *xyz)
+{
+    MetricArgs a;
+    a.dm = dims_of(g);
+    a.ndim = g->cfg.ndim;
+    for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 3; ++c) a.off[d][c] = g->cfg.off[d][c];
+    if (a.ndim == 2) {
+        a.off[2][0] = 0.0;
+        a.off[2][1] = 0.0;
+        a.off[2][2] = 1.0;
+        for (int d = 0; d < 2; ++d) a.off[d][2] = 0.0;
+    }
+    a.xyz = xyz;
+    a.xyz_t = nullptr;
+    a.dx = g->scratch;
+    a.m = g->metrics;
+    a.flags = g->flags;
+    unsigned blocks = unsigned((a.dm.ncell + kBlock - 1) / kBlock);
+    Timed timed(g, GBR_K_METRICS);
+    hipLaunchKernelGGL(k_coord_deriv_c4, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    hipLaunchKernelGGL(k_cell_metrics_nonfp, dim3(blocks), dim3(kBlock), 0, g->stream, a);
+    hipLaunchKernelGGL(k_face_metrics_c4, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }
 

@@ -124,6 +124,8 @@ def lib():
     L.gbr_timing_collect.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_long)]
     L.gbr_last_error.argtypes = [_VP]
     L.gbr_last_error.restype = C.c_char_p
+    L.gbr_metrics_nonfp.argtypes = [_PP, C.c_int, _PP]
+    L.gbr_metrics_nonfp.restype = C.c_int
     L.gbr_diagnostics.argtypes = [_PP, C.c_int, _PP, _PP, _PP]
     L.gbr_diagnostics.restype = C.c_int
     L.gbr_batch_create.argtypes = [_PP, C.c_int, _PP, C.c_int, C.POINTER(_VP)]
@@ -219,6 +221,11 @@ def gbr_metrics(handles, xyz, xyz_t=None):
     n = len(handles)
     xt = _arr(xyz_t) if xyz_t is not None else None
     _check(lib().gbr_metrics(_arr(handles), n, _arr(xyz), xt), handles[0] if n else None)
+
+
+def gbr_metrics_nonfp(handles, xyz):
+    n = len(handles)
+    _check(lib().gbr_metrics_nonfp(_arr(handles), n, _arr(xyz)), handles[0] if n else None)
 
 
 def gbr_rhs(handles, Q, res):
@@ -341,6 +348,9 @@ class Grid:
 
     def metrics(self, xyz, xyz_t=None):
         gbr_metrics([self.h], [xyz], [xyz_t] if xyz_t is not None else None)
+
+    def metrics_nonfp(self, xyz):
+        gbr_metrics_nonfp([self.h], [xyz])
 
     def rhs(self, Q, res):
         gbr_rhs([self.h], [Q], [res])
