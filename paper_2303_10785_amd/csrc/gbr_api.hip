@@ -336,9 +336,7 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
             else
                 e = gbr::launch_fill(gg, gg->dt, 1, cfl_or_dt);
         }
-        const long nq = (long)gg->nvar * gg->ncell;
-        if (e == hipSuccess) e = gbr::launch_copy(gg, gg->qn, Q[b], nq);
-        for (int st = 0; st < 3 && e == hipSuccess; ++st) e = gbr::launch_step_stage(gg, st, gg->dt, gg->qn, Q[b]);
+        for (int st = 0; st < 3 && e == hipSuccess; ++st) e = gbr::launch_step_stage(gg, st, gg->dt, Q[b], gg->qn);
         if (e == hipSuccess && dt_out && dt_out[b]) e = gbr::launch_copy(gg, dt_out[b], gg->dt, 1);
         if (e != hipSuccess) return hip_fail(gg, e, "step launch");
     }

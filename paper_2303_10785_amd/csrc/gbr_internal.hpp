@@ -22,7 +22,7 @@ struct gbr_grid_s {
     double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
     double *prim2 = nullptr;     // 6 * ncell: second primitive buffer (gbr_step stages alternate)
     double *partial = nullptr;   // kReducePartials: per-block minima of the time-step reduction
-    double *qn = nullptr;        // nvar * ncell: RK stage-0 state (gbr_step)
+    double *qn = nullptr;        // nvar * ncell: RK stage buffer (gbr_step) / batch stage buffer
     double *res = nullptr;       // nvar * ncell: RHS (gbr_step; float data in FP32-bulk)
     double *dt = nullptr;        // 1: time step of the last gbr_step / gbr_cfl
     unsigned long long *dtmin = nullptr;  // 1: min-reduction word (bit pattern of a positive double)
@@ -100,7 +100,8 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
 // may be null).
 hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, double *integrals);
 // RHS and SSP-RK3 stage of gbr_step with the stage fused into the last sweep.
-hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q);
+// Q: state at the start of the step, advanced in place; S: stage buffer.
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);

@@ -35,6 +35,9 @@ namespace gbr {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef GBR_IG4_UNROLL
+#define GBR_IG4_UNROLL 4
+#endif
 #ifndef GBR_TS_CROSS
 #define GBR_TS_CROSS 16
 #endif
@@ -59,7 +62,8 @@ struct RhsArgs {
     const double *m;  // metrics (always double)
     int *flags;
     // SSP-RK3 stage fused into the last sweep (gbr_step only)
-    double *Qw;        // state updated in place
+    const double *Qin; // stage input state
+    double *Qout;      // stage output state (may equal Qin or Qn: each cell is read before it is written)
     const double *Qn;  // stage-0 state
     const double *dt;  // time step (device)
     double ca, cb;     // stage coefficients
@@ -132,25 +136,31 @@ __device__ __forceinline__ R ducros_theta(const R gd[3][4], const double *m, lon
 // MIG4 gradients (Eq. IG4_grads) along direction D of the six primitives
 // with the explicit wide stencil that equals the implicit scheme
 // (gbr_stencil.hip): f'_i = sum_j w_j (f_{i+j} - f_{i-j}), periodic. A
-// workgroup stages a segment of IG4_TS cells along D (plus a halo of
-// kIg4Half cells on each side) for IG4_TC lines in LDS, one variable at a
-// time; along xi one line per workgroup, along eta / zeta 16 lines side by
-// side (i fastest, coalesced) with each thread owning 4 cells along D.
+// workgroup stages a segment of TS cells along D (plus a halo of kIg4Half
+// cells on each side) for TC lines in LDS, one variable at a time; each
+// thread owns 4 consecutive cells of a line and accumulates them with two
+// sliding register windows (about 25 LDS reads per output instead of 96).
+// Along xi 4 lines of 256 cells, along eta / zeta 16 lines (i fastest,
+// coalesced) of 64 cells.
 template <int D>
 struct Ig4Tile {
-    static constexpr int TC = (D == 0) ? 1 : 16;
+    static constexpr int TC = (D == 0) ? 4 : 16;
     static constexpr int TS = (D == 0) ? 256 : 64;
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
     static constexpr int OD = (D == 2) ? 1 : 2;
     static constexpr int LEN = TS + 2 * kIg4Half;
+    // LDS position of (s, c): along s contiguous for xi, c contiguous otherwise
+    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * LEN + sl : sl * TC + cl; }
+    static constexpr int ST = (D == 0) ? 1 : TC;
 };
 
 template <int D, int NDIM, class R>
 __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st)
 {
     using T = Ig4Tile<D>;
-    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN;
+    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN, ST = T::ST;
+    static_assert(TC * (TS / 4) == kBlock, "four cells per thread");
     __shared__ R buf[LEN * TC];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
@@ -160,33 +170,54 @@ __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st
     const int c0 = (blockIdx.x / tiles_s) * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
+    // this thread: cells 4 sq .. 4 sq + 3 of line cl
+    const int cl = (D == 0) ? tid / (TS / 4) : tid % TC;
+    const int sq = (D == 0) ? tid % (TS / 4) : tid / TC;
     R *outs[6] = {a.grad2 + (D * 2 + 0) * N, a.grad + (D * 4 + 0) * N, a.grad + (D * 4 + 1) * N,
                   a.grad + (D * 4 + 2) * N, a.grad2 + (D * 2 + 1) * N, a.grad + (D * 4 + 3) * N};
     for (int v = 0; v < 6; ++v) {
-        if (NDIM == 2 && v == 3) {
-            // w is identically zero in 2-D
-            for (int q = tid; q < TS * TC; q += kBlock) {
-                const int sl = q / TC, cl = q % TC;
-                if (s0 + sl < ns && c0 + cl < nc) outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = R(0);
+        R acc[4] = {R(0), R(0), R(0), R(0)};
+        if (!(NDIM == 2 && v == 3)) {  // w is identically zero in 2-D
+            const R *f = a.prim + (long)v * N;
+            for (int e = tid; e < LEN * TC; e += kBlock) {
+                const int sl = (D == 0) ? e % LEN : e / TC;
+                const int cc = (D == 0) ? e / LEN : e % TC;
+                buf[T::at(sl, cc)] =
+                    f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cc, nc - 1), o)];
             }
-            continue;
-        }
-        const R *f = a.prim + (long)v * N;
-        for (int e = tid; e < LEN * TC; e += kBlock) {
-            const int sl = e / TC, cl = e % TC;
-            buf[e] = f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cl, nc - 1), o)];
-        }
-        __syncthreads();
-        for (int q = tid; q < TS * TC; q += kBlock) {
-            const int sl = q / TC, cl = q % TC;
-            if (s0 + sl < ns && c0 + cl < nc) {
-                const R *c = buf + (sl + H) * TC + cl;
-                R acc = R(0);
-                for (int j = 1; j <= H; ++j) acc += R(st.w[j]) * (c[j * TC] - c[-j * TC]);
-                outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = acc;
+            __syncthreads();
+            // sliding windows: at step j, P[q] = f(4 sq + q + j) and
+            // M[q] = f(4 sq + q - j); each step loads one new value per side
+            const R *c = buf + T::at(4 * sq + H, cl);
+            R P[4], M[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                P[q] = c[(q + 1) * ST];
+                M[q] = c[(q - 1) * ST];
             }
+#pragma unroll GBR_IG4_UNROLL
+            for (int j = 1; j <= H; ++j) {
+                const R w = R(st.w[j]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] += w * (P[q] - M[q]);
+                if (j < H) {
+                    P[0] = P[1];
+                    P[1] = P[2];
+                    P[2] = P[3];
+                    P[3] = c[(4 + j) * ST];
+                    M[3] = M[2];
+                    M[2] = M[1];
+                    M[1] = M[0];
+                    M[0] = c[(-1 - j) * ST];
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int sl = 4 * sq + q;
+            if (s0 + sl < ns && c0 + cl < nc) outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = acc[q];
+        }
     }
 }
 
@@ -541,10 +572,10 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
                 // App. B with Eq. time-split: Q <- a Qn + b (Q + dt J (Res - (1/J)_t Q))
                 const R res = *r - d;
                 const long e = (long)ov * N + ch;
-                const double q = a.Qw[e];
+                const double q = a.Qin[e];
                 const double L = J * (double(res) - it * q);
                 qnew[ov] = a.ca * a.Qn[e] + a.cb * (q + dt * L);
-                a.Qw[e] = qnew[ov];
+                a.Qout[e] = qnew[ov];
             }
         }
         if (MODE == 2 && a.prim_out) {
@@ -841,7 +872,8 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;
     a.flags = g->flags;
-    a.Qw = nullptr;
+    a.Qin = nullptr;
+    a.Qout = nullptr;
     a.Qn = nullptr;
     a.dt = nullptr;
     a.ca = a.cb = 0.0;
@@ -909,18 +941,22 @@ hipError_t diag_typed(gbr_grid_s *g, const double *Q, double *fields, double *in
 static const double kRkA[3] = {0.0, 0.75, 1.0 / 3.0};
 static const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 
-// One gbr_step stage: stage 0 forms the primitives of Q into the first
-// primitive buffer; each stage reads the buffer of its index parity and the
-// fused last sweep writes the next stage's primitives into the other one.
+// One gbr_step stage. Q is the state at the start of the step (Qn of every
+// stage) and S a stage buffer: stage 0 maps Q to S, stage 1 updates S in
+// place and stage 2 maps S back into Q, so Q needs no copy. Stage 0 forms
+// the primitives of Q into the first primitive buffer; each stage reads the
+// buffer of its index parity and the fused last sweep writes the next
+// stage's primitives into the other one.
 template <class R>
-hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q)
+hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S)
 {
     RhsArgs<R> a = make_args<R>(g, Q, static_cast<R *>(static_cast<void *>(g->res)));
     R *buf[2] = {reinterpret_cast<R *>(g->prim), reinterpret_cast<R *>(g->prim2)};
     a.prim = buf[stage % 2];
     a.prim_out = stage < 2 ? buf[(stage + 1) % 2] : nullptr;
-    a.Qw = Q;
-    a.Qn = Qn;
+    a.Qin = stage == 0 ? Q : S;
+    a.Qout = stage == 2 ? Q : S;
+    a.Qn = Q;
     a.dt = dt;
     a.ca = kRkA[stage];
     a.cb = kRkB[stage];
@@ -961,10 +997,10 @@ hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, do
     return diag_typed<double>(g, Q, fields, integrals);
 }
 
-hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q)
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S)
 {
-    if (g->cfg.precision == GBR_FP32_BULK) return step_stage_typed<float>(g, stage, dt, Qn, Q);
-    return step_stage_typed<double>(g, stage, dt, Qn, Q);
+    if (g->cfg.precision == GBR_FP32_BULK) return step_stage_typed<float>(g, stage, dt, Q, S);
+    return step_stage_typed<double>(g, stage, dt, Q, S);
 }
 
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
