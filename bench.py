@@ -48,7 +48,6 @@ ALG_BYTES_PER_CELL = {
     "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 40 + 96 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     "cfl": 40 + 72 + 24,                  # Q, 9 cell metrics, 3 temporal metrics
-    "copy": 80,
 }
 
 
@@ -302,9 +301,10 @@ def main():
     dt = torch.zeros(1, dtype=torch.float64, device=dev)
     ncell = NI * NJ * NK
 
-    # a plain copy of the state (518 MB each way, outside the timed region):
-    # the calibration kernel for the HBM counter runs of profiles/
-    calib = Q.clone()
+    # a streaming pass over the state (518 MB read, 518 MB written, outside
+    # the timed region; torch's elementwise negation, a copy with a sign
+    # flip): the calibration kernel for the HBM counter runs of profiles/
+    calib = torch.neg(Q)
     del calib
     log(f"bench: {args.warmup} warmup steps")
     for _ in range(args.warmup):
@@ -348,7 +348,7 @@ def main():
         if cnt:
             breakdown[k] = {"ms_per_launch": ms / cnt, "launches": cnt,
                             "share": ms / ms_total}
-    dom = max((k for k in breakdown if k in ALG_BYTES_PER_CELL and k != "copy"),
+    dom = max((k for k in breakdown if k in ALG_BYTES_PER_CELL),
               key=lambda k: breakdown[k]["ms_per_launch"] * breakdown[k]["launches"])
     alg = ALG_BYTES_PER_CELL[dom] * ncell
     avg_s = breakdown[dom]["ms_per_launch"] * 1e-3
