@@ -71,6 +71,9 @@ class _Cfg(C.Structure):
         ("alpha_mp", C.c_double),
         ("beta_mp", C.c_double),
         ("alpha_d", C.c_double),
+        ("bc", C.c_int * 6),
+        ("sigma", C.POINTER(C.c_double)),
+        ("qref", C.c_double * 5),
     ]
 
 
@@ -78,6 +81,8 @@ DEFAULTS = dict(gamma=1.4, Pr=0.71, Re=1e4, Mref=1.0, suth=110.4 / 293.0,
                 viscous=False, limiter="mp", theta_c=0.5, alpha_mp=4.0, beta_mp=4.0,
                 alpha_d=4.0, scheme="meg6")
 SCHEMES = {"meg6": 0, "mig4": 1}
+BC = {"periodic": 0, "inflow": 1, "outflow": 2, "wall": 3}
+NG = 6  # ghost layers on each non-periodic side (REF_NG)
 
 _lib = None
 _P = C.POINTER(C.c_double)
@@ -114,6 +119,11 @@ def lib():
         L.ref_diagnostics.restype = C.c_int
         L.ref_mp_limit.argtypes = [C.c_double] * 9
         L.ref_mp_limit.restype = C.c_double
+        L.ref_bline_derivs.argtypes = [_P, C.c_int, _P, _P]
+        L.ref_bline_derivs.restype = C.c_int
+        L.ref_bline_faces.argtypes = [_P, C.c_int, _P]
+        L.ref_bline_faces.restype = C.c_int
+        L.ref_apply_bc.argtypes = [cfgp, _P, _P]
         L.ref_hllc.argtypes = [_P, _P, _P, C.c_double, _P]
         L.ref_euler_flux.argtypes = [_P, _P, C.c_double, _P]
         _lib = L
@@ -145,6 +155,19 @@ def make_cfg(grid, **params):
         c.off[q] = float(off[q])
     for k in ("gamma", "Pr", "Re", "Mref", "suth", "theta_c", "alpha_mp", "beta_mp", "alpha_d"):
         setattr(c, k, float(p[k]))
+    bc = grid.get("bc")
+    for d in range(3):
+        for side in range(2):
+            t = bc[d][side] if bc is not None and d < len(bc) else "periodic"
+            c.bc[d * 2 + side] = BC[t] if isinstance(t, str) else int(t)
+    sigma = p.get("sigma")
+    if sigma is not None:
+        keep = _f64(sigma).reshape(-1)
+        assert keep.size == _ncell(grid)
+        c.sigma = keep.ctypes.data_as(_P)
+        c._keep = keep  # the array must outlive the call
+        for q, v in enumerate(p.get("qref", (1.0, 0.0, 0.0, 0.0, 1.0 / 1.4))):
+            c.qref[q] = float(v)
     return c
 
 
@@ -170,6 +193,8 @@ def metrics(grid, nonfp=False, **params):
         keep = _f64(xt) if xt is not None else None
         rc = lib().ref_metrics(C.byref(cfg), _ptr(xyz), _ptr(keep) if keep is not None else None,
                                _ptr(m))
+    if rc == -2:
+        raise NotImplementedError("oracle metrics: unsupported combination (rc=-2)")
     if rc != 0:
         raise ValueError("oracle metrics: non-positive Jacobian (rc=%d)" % rc)
     return m
@@ -276,6 +301,42 @@ def line_ig4_face(v, shift=0.0):
 def line_ig4_dcomp(v, shift=0.0):
     """Difference of the IG4 interface values (Eq. FP-interp2)."""
     return _line_checked("ref_line_ig4_dcomp", v, shift)
+
+
+def bline_derivs(v):
+    """App. C first and second derivatives on a non-periodic line (m >= 12)."""
+    v = _f64(v)
+    p, h = np.zeros_like(v), np.zeros_like(v)
+    if lib().ref_bline_derivs(_ptr(v), len(v), _ptr(p), _ptr(h)) != 0:
+        raise ValueError("line too short")
+    return p, h
+
+
+def bline_faces(v):
+    """App. C interface values F[0..m] of a non-periodic line (m >= 12)."""
+    v = _f64(v)
+    F = np.zeros(len(v) + 1)
+    if lib().ref_bline_faces(_ptr(v), len(v), _ptr(F)) != 0:
+        raise ValueError("line too short")
+    return F
+
+
+def apply_bc(grid, m, Q, **params):
+    """Q with its ghost cells set from the grid's boundary types (a copy)."""
+    cfg = make_cfg(grid, **params)
+    out = _f64(Q).copy()
+    lib().ref_apply_bc(C.byref(cfg), _ptr(_f64(m)), _ptr(out))
+    return out
+
+
+def interior(grid):
+    """Index tuple (slices over [nk][nj][ni]) of the interior cells."""
+    bc = grid.get("bc")
+    sl = []
+    for d in (2, 1, 0):
+        bounded = bc is not None and d < len(bc) and bc[d][0] != "periodic"
+        sl.append(slice(NG, grid["n"][d] - NG) if bounded else slice(None))
+    return tuple(sl)
 
 
 def eigvec(nrm, rho, a):

@@ -368,8 +368,12 @@ static void field_window(const ref_cfg *g, const double *f, const int ijk[3], in
  * metric identities, freestream on static and deforming grids.            */
 static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m);
 
+static int metrics_bounded(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m);
+static int any_bounded(const ref_cfg *g);
+
 int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
 {
+    if (any_bounded(g)) return metrics_bounded(g, xyz, xyz_t, m);
     if (g->scheme == REF_SCHEME_MIG4) return metrics_mig4(g, xyz, xyz_t, m);
     const long N = ncell_of(g);
     double *dx = (double *)malloc(sizeof(double) * 9 * N); /* dx[(d*3+c)*N] = D_d of coord c */
@@ -613,6 +617,303 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
     free(dx); free(ta); free(tb);
     if (rc) return -1;
     return bad ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-periodic boundaries (Sec. 6, App. C).                                */
+/* A non-periodic direction d stores REF_NG ghost layers on each side: the  */
+/* interior cells are REF_NG .. n[d] - REF_NG - 1. Ghost cells carry        */
+/* primitive states set from the boundary type; they have no metrics of     */
+/* their own (Sec. 6), so the metrics of interior cells come from App. C    */
+/* and every ghost slot holds a copy of the nearest interior value.         */
+/* ------------------------------------------------------------------------ */
+static int is_bounded(const ref_cfg *g, int d) { return d < g->ndim && g->bc[d][0] != REF_BC_PERIODIC; }
+
+static int any_bounded(const ref_cfg *g)
+{
+    for (int d = 0; d < 3; ++d)
+        if (is_bounded(g, d)) return 1;
+    return 0;
+}
+
+static int in_interior(const ref_cfg *g, const int ijk[3])
+{
+    for (int d = 0; d < 3; ++d)
+        if (is_bounded(g, d) && (ijk[d] < REF_NG || ijk[d] >= g->n[d] - REF_NG)) return 0;
+    return 1;
+}
+
+/* Nearest interior cell; for a face slot of family f (face_of >= 0) the
+ * f index is clamped to the faces REF_NG - 1 .. n - REF_NG - 1, which hold
+ * the interfaces from the low boundary face to the high one.              */
+static long clamp_cell(const ref_cfg *g, const int ijk[3], int face_of)
+{
+    int t[3] = {ijk[0], ijk[1], ijk[2]};
+    for (int d = 0; d < 3; ++d) {
+        if (!is_bounded(g, d)) continue;
+        int lo = (d == face_of) ? REF_NG - 1 : REF_NG, hi = g->n[d] - REF_NG - 1;
+        if (t[d] < lo) t[d] = lo;
+        if (t[d] > hi) t[d] = hi;
+    }
+    return cell_index(g, t);
+}
+
+/* App. C closures. s = +1 at the low end (v[0] is the boundary cell), s = -1
+ * at the high end (the mirror image: derivatives change sign).
+ * Second-order one-sided first derivative at the boundary cell.           */
+static double one_sided2(const double *v, int s)
+{
+    return s * (-1.5 * v[0] + 2.0 * v[s] - 0.5 * v[2 * s]);
+}
+
+/* Fourth-order partially one-sided derivative at the second cell. The
+ * printed stencil runs over cells i .. i+4, which is this formula centred
+ * one cell further in; the closure is read as the standard one on cells
+ * i-1 .. i+3 (fourth order at cell i; the quadratic-exactness pin fails for
+ * the printed placement).                                                 */
+static double part_one_sided4(const double *v, int s)
+{
+    return s * (-0.25 * v[-s] - (5.0 / 6.0) * v[0] + 1.5 * v[s] - 0.5 * v[2 * s] + (1.0 / 12.0) * v[3 * s]);
+}
+
+/* Fourth-order central first derivative at the third cell. */
+static double central4(const double *v) { return (2.0 / 3.0) * (v[1] - v[-1]) - (1.0 / 12.0) * (v[2] - v[-2]); }
+
+int ref_bline_derivs(const double *v, int m, double *p, double *h)
+{
+    if (m < 12) return -1;
+    /* x': one-sided, partially one-sided, central-4 closures, E6 inside */
+    p[0] = one_sided2(v, 1);
+    p[1] = part_one_sided4(v + 1, 1);
+    p[2] = central4(v + 2);
+    for (int c = 3; c <= m - 4; ++c) p[c] = e6(v + c);
+    p[m - 3] = central4(v + m - 3);
+    p[m - 2] = part_one_sided4(v + m - 2, -1);
+    p[m - 1] = one_sided2(v + m - 1, -1);
+    /* x'': the same two closures applied to x' at the first two cells; at
+     * the third cell the printed formula is the Hermite form of Step-1 with
+     * the sign of the second difference flipped, read as the Hermite form
+     * (exact for quadratics only with that sign); Hermite inside.         */
+    h[0] = one_sided2(p, 1);
+    h[1] = part_one_sided4(p + 1, 1);
+    for (int c = 2; c <= m - 3; ++c) h[c] = hermite(v + c, p + c);
+    h[m - 2] = part_one_sided4(p + m - 2, -1);
+    h[m - 1] = one_sided2(p + m - 1, -1);
+    return 0;
+}
+
+/* Interface values (App. C): the face next to the boundary face takes the
+ * inward cell's biased state alone (as printed for i = 1), the next faces
+ * the central average of Eq. FP-interp. The boundary face itself, which the
+ * appendix leaves out, takes the boundary cell's state extrapolated to it.
+ * The high end mirrors the low one.                                       */
+int ref_bline_faces(const double *v, int m, double *F)
+{
+    if (m < 12) return -1;
+    double *p = (double *)malloc(sizeof(double) * m), *h = (double *)malloc(sizeof(double) * m);
+    if (!p || !h) { free(p); free(h); return -2; }
+    ref_bline_derivs(v, m, p, h);
+#define LEFT(c) (v[c] + 0.5 * p[c] + h[c] / 12.0)   /* state at c + 1/2 */
+#define RIGHT(c) (v[c] - 0.5 * p[c] + h[c] / 12.0)  /* state at c - 1/2 */
+    F[0] = RIGHT(0);
+    F[1] = RIGHT(1);
+    for (int f = 2; f <= m - 2; ++f) F[f] = 0.5 * (LEFT(f - 1) + RIGHT(f));
+    F[m - 1] = LEFT(m - 2);
+    F[m] = LEFT(m - 1);
+#undef LEFT
+#undef RIGHT
+    free(p); free(h);
+    return 0;
+}
+
+/* Periodic line extended by F[k + n] = F[k] + J[k] (J may be NULL): the
+ * central interface value at a + 1/2 for any integer a. */
+static double pline_face_at(const double *F, const double *J, int n, int a)
+{
+    double w[10];
+    for (int q = -4; q <= 5; ++q) {
+        int b = a + q, r = mod_n(b, n);
+        w[q + 4] = F[r] + (J ? (double)floor_div(b, n) * J[r] : 0.0);
+    }
+    return face_central(w + 4);
+}
+
+/* Line job on a grid with non-periodic directions: along a periodic d the
+ * central operators of ref_metrics on the extended line; along a bounded d
+ * App. C on the interior cells of the line (ghost entries are left alone). */
+static int bjob_fn(void *ctx, const long *cells)
+{
+    line_job *jb = (line_job *)ctx;
+    const ref_cfg *g = jb->g;
+    const int n = g->n[jb->d];
+    double *F = (double *)calloc((size_t)n + 1, sizeof(double));
+    double *J = (double *)calloc((size_t)n + 1, sizeof(double));
+    double *f = (double *)calloc((size_t)n + 1, sizeof(double));
+    int rc = (!F || !J || !f) ? -1 : 0;
+    for (int k = 0; k < n && !rc; ++k) {
+        if (jb->faces) {
+            F[k] = jb->src[cells[k]];
+        } else {
+            double a = jb->fac ? jb->fac[cells[k]] : 1.0;
+            F[k] = a * jb->xc[cells[k]];
+            J[k] = a * jb->jump;
+        }
+    }
+    if (!rc && !is_bounded(g, jb->d)) {
+        for (int k = 0; k < n; ++k) {
+            double up = pline_face_at(F, jb->faces ? NULL : J, n, k);
+            jb->out[cells[k]] = jb->faces ? up : up - pline_face_at(F, J, n, k - 1);
+        }
+    } else if (!rc) {
+        const int m = n - 2 * REF_NG;
+        rc = ref_bline_faces(F + REF_NG, m, f);
+        if (!rc) {
+            if (jb->faces)
+                for (int q = 0; q <= m; ++q) jb->out[cells[REF_NG - 1 + q]] = f[q];
+            else
+                for (int k = 0; k < m; ++k) jb->out[cells[REF_NG + k]] = f[k + 1] - f[k];
+        }
+    }
+    free(F); free(J); free(f);
+    return rc;
+}
+
+static int run_bjob(line_job jb) { return for_lines(jb.g, jb.d, bjob_fn, &jb); }
+
+/* Metrics of a static grid with non-periodic directions: the steps of
+ * ref_metrics (Eq. GCL_metrics, Jac-matrix, interp-formulae) with App. C
+ * along the bounded directions, lines processed whole in the coordinates
+ * as given; then every ghost slot copies the nearest interior one.
+ * Pins: exactness on affine grids, discrete metric identities and
+ * freestream with the boundary faces included, and the App. C line pins. */
+static int metrics_bounded(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
+{
+    if (g->moving || xyz_t || g->scheme != REF_SCHEME_MEG6) return -2;
+    for (int d = 0; d < 3; ++d)
+        if (is_bounded(g, d) && g->n[d] - 2 * REF_NG < 12) return -2;
+    const long N = ncell_of(g);
+    double *dx = (double *)calloc((size_t)9 * N, sizeof(double));
+    double *ta = (double *)calloc((size_t)N, sizeof(double));
+    double *tb = (double *)calloc((size_t)N, sizeof(double));
+    int rc = (!dx || !ta || !tb) ? -1 : 0;
+    /* Step 1: coordinate derivatives D_d(x_c). */
+    for (int d = 0; d < 3 && !rc; ++d)
+        for (int c = 0; c < 3 && !rc; ++c) {
+            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0};
+            rc = run_bjob(jb);
+        }
+    /* Step 2: hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2]. */
+    for (int d = 0; d < 3 && !rc; ++d) {
+        int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        for (int c = 0; c < 3 && !rc; ++c) {
+            int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0};
+            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0};
+            rc = run_bjob(ja);
+            if (!rc) rc = run_bjob(jc);
+            if (!rc)
+                for (long idx = 0; idx < N; ++idx) m[REF_M_HAT(d, c) * N + idx] = ta[idx] - tb[idx];
+        }
+    }
+    int bad = 0;
+    if (!rc) {
+        /* Step 3: 1/J = det[D_d x_c]; unhatted d_c = J hat(d)_c. Step 4:
+         * static grid, no temporal metrics. */
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            const double *a = dx + idx;
+#define DX(d, c) a[((d) * 3 + (c)) * N]
+            double invj = DX(0, 0) * (DX(1, 1) * DX(2, 2) - DX(1, 2) * DX(2, 1))
+                        - DX(0, 1) * (DX(1, 0) * DX(2, 2) - DX(1, 2) * DX(2, 0))
+                        + DX(0, 2) * (DX(1, 0) * DX(2, 1) - DX(1, 1) * DX(2, 0));
+#undef DX
+            if (in_interior(g, ijk) && !(invj > 0.0)) bad = 1;
+            m[REF_M_INVJ * N + idx] = invj;
+            m[REF_M_J * N + idx] = 1.0 / invj;
+            for (int d = 0; d < 3; ++d) {
+                for (int c = 0; c < 3; ++c)
+                    m[REF_M_UNHAT(d, c) * N + idx] = m[REF_M_HAT(d, c) * N + idx] / invj;
+                m[REF_M_HATT(d) * N + idx] = 0.0;
+                m[REF_M_UNHATT(d) * N + idx] = 0.0;
+            }
+            m[REF_M_INVJT * N + idx] = 0.0;
+        }
+    }
+    /* Step 5: interface values per family f. */
+    for (int f = 0; f < 3 && !rc; ++f) {
+        int src[13], dst[13], q = 0;
+        for (int c = 0; c < 3; ++c) { src[q] = REF_M_HAT(f, c); dst[q++] = REF_M_FHAT(f, c); }
+        src[q] = REF_M_HATT(f); dst[q++] = REF_M_FHATT(f);
+        for (int e = 0; e < 3; ++e)
+            for (int c = 0; c < 3; ++c) { src[q] = REF_M_UNHAT(e, c); dst[q++] = REF_M_FUNHAT(f, e, c); }
+        for (q = 0; q < 13 && !rc; ++q) {
+            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1};
+            rc = run_bjob(jb);
+        }
+    }
+    /* Step 6: ghost slots copy the nearest interior (or boundary-face) value. */
+    if (!rc)
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            long cc = clamp_cell(g, ijk, -1);
+            if (cc != idx)
+                for (int sl = 0; sl < 27; ++sl) m[(long)sl * N + idx] = m[(long)sl * N + cc];
+            for (int f = 0; f < 3; ++f) {
+                long fc = clamp_cell(g, ijk, f);
+                if (fc == idx) continue;
+                for (int sl = REF_M_FHAT(f, 0); sl < REF_M_FHAT(f, 0) + 13; ++sl)
+                    m[(long)sl * N + idx] = m[(long)sl * N + fc];
+            }
+        }
+    free(dx); free(ta); free(tb);
+    if (rc) return rc;
+    return bad ? 1 : 0;
+}
+
+/* Ghost cells of Q (Sec. 6; the table of ghost-cell expressions is not in
+ * the text available, so the standard forms are used): Dirichlet inflow
+ * ghosts keep the state stored in them; zero-gradient outflow ghosts copy
+ * the boundary cell of their line; slip-wall ghosts mirror the interior
+ * cell at the same depth with the momentum component along the unit normal
+ * of the boundary face reversed. Directions are filled in order over the
+ * full extent of the others, so corner ghosts take the later direction's
+ * rule applied to the earlier one's values.
+ * Pins: a wall (mirror) or Dirichlet boundary on an affine grid reproduces
+ * the periodic residual of the mirrored / extended flow.                 */
+void ref_apply_bc(const ref_cfg *g, const double *m, double *Q)
+{
+    const long N = ncell_of(g);
+    const int nv = g->ndim + 2;
+    for (int d = 0; d < g->ndim; ++d) {
+        if (!is_bounded(g, d)) continue;
+        const int n = g->n[d];
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            int side = -1, depth = 0;
+            if (ijk[d] < REF_NG) { side = 0; depth = REF_NG - 1 - ijk[d]; }
+            else if (ijk[d] >= n - REF_NG) { side = 1; depth = ijk[d] - (n - REF_NG); }
+            if (side < 0) continue;
+            const int type = g->bc[d][side];
+            if (type == REF_BC_INFLOW) continue;
+            int src[3] = {ijk[0], ijk[1], ijk[2]}, face[3] = {ijk[0], ijk[1], ijk[2]};
+            if (type == REF_BC_OUTFLOW) src[d] = side ? n - REF_NG - 1 : REF_NG;
+            else src[d] = side ? n - REF_NG - 1 - depth : REF_NG + depth;
+            face[d] = side ? n - REF_NG - 1 : REF_NG - 1;
+            const long sc = cell_index(g, src);
+            for (int v = 0; v < nv; ++v) Q[v * N + idx] = Q[v * N + sc];
+            if (type == REF_BC_WALL) {
+                const long fc = cell_index(g, face);
+                double nr[3], nn = 0.0, mn = 0.0;
+                for (int c = 0; c < 3; ++c) { nr[c] = m[REF_M_FHAT(d, c) * N + fc]; nn += nr[c] * nr[c]; }
+                nn = sqrt(nn);
+                for (int c = 0; c < g->ndim; ++c) { nr[c] /= nn; mn += Q[(1 + c) * N + idx] * nr[c]; }
+                for (int c = 0; c < g->ndim; ++c) Q[(1 + c) * N + idx] -= 2.0 * mn * nr[c];
+            }
+        }
+    }
 }
 
 /* Non-freestream-preserving metrics of App. D (negative control only):
@@ -1113,17 +1414,39 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
     const long N = ncell_of(g);
     const int nv = g->ndim + 2;
     const int nf = g->ndim;
+    const int bnd = any_bounded(g);
+    const double *Qs = Q;  /* the state as given (sponge term) */
+    double *Qb = NULL;
+    if (bnd) {
+        /* ghost states from the boundary types (Sec. 6) */
+        if (g->scheme != REF_SCHEME_MEG6) return -2;
+        Qb = (double *)malloc(sizeof(double) * nv * N);
+        if (!Qb) return -1;
+        memcpy(Qb, Q, sizeof(double) * nv * N);
+        ref_apply_bc(g, m, Qb);
+        Q = Qb;
+    }
     double *grad = (double *)calloc((size_t)12 * N, sizeof(double));
     double *theta = (double *)calloc((size_t)N, sizeof(double));
     double *phi = (double *)malloc(sizeof(double) * 5 * N);
     double *pgrad = NULL;
-    if (!grad || !theta || !phi) { free(grad); free(theta); free(phi); return -1; }
+    if (!grad || !theta || !phi) { free(grad); free(theta); free(phi); free(Qb); return -1; }
     ref_gradients(g, Q, grad);
     if (g->scheme == REF_SCHEME_MIG4) {
         pgrad = (double *)malloc(sizeof(double) * 18 * N);
         if (!pgrad || ig4_prim_grads(g, Q, pgrad)) { free(grad); free(theta); free(phi); free(pgrad); return -1; }
     }
-    if (g->limiter == REF_LIM_DUCROS) ref_sensor(g, m, grad, theta);
+    if (g->limiter == REF_LIM_DUCROS) {
+        ref_sensor(g, m, grad, theta);
+        /* ghost cells have no metrics of their own: their sensor value is
+         * that of the nearest interior cell */
+        if (bnd)
+            for (long idx = 0; idx < N; ++idx) {
+                int ijk[3];
+                unpack(g, idx, ijk);
+                theta[idx] = theta[clamp_cell(g, ijk, -1)];
+            }
+    }
     int bad = 0;
     for (long idx = 0; idx < N; ++idx) {
         prim_t s = primitive(g, Q, idx);
@@ -1136,7 +1459,14 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
             int ijk[3];
             double ph[5];
             unpack(g, idx, ijk);
-            if (face_flux(g, m, Q, grad, pgrad, theta, f, ijk, idx, ph)) bad = 1;
+            int fail = face_flux(g, m, Q, grad, pgrad, theta, f, ijk, idx, ph);
+            if (fail && bnd) {
+                /* only interfaces of interior cells count */
+                int up[3] = {ijk[0], ijk[1], ijk[2]};
+                up[f] = (ijk[f] + 1) % g->n[f];
+                fail = in_interior(g, ijk) || in_interior(g, up);
+            }
+            if (fail) bad = 1;
             for (int s = 0; s < 5; ++s) phi[s * N + idx] = ph[s];
         }
 #pragma omp parallel for schedule(static)
@@ -1150,10 +1480,38 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
             }
         }
     }
+    if (bnd)
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            if (!in_interior(g, ijk))
+                for (int v = 0; v < nv; ++v) res[v * N + idx] = 0.0;
+        }
+    if (g->sigma) {
+        /* sponge (Sec. 8.3, after Bodony): d Q / dt gains -sigma (Q - Q_ref),
+         * i.e. Res gains -sigma (Q - Q_ref) / J with 1/J the cell volume */
+        const double *P = g->qref;
+        double qr[5];
+        qr[0] = P[0];
+        qr[1] = P[0] * P[1];
+        qr[2] = P[0] * P[2];
+        qr[3] = P[0] * P[3];
+        qr[4] = P[4] / (g->gamma - 1.0) + 0.5 * P[0] * (P[1] * P[1] + P[2] * P[2] + P[3] * P[3]);
+        for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            if (!in_interior(g, ijk)) continue;
+            for (int v = 0; v < nv; ++v) {
+                int s = (nv == 4 && v == 3) ? 4 : v;
+                res[v * N + idx] -= g->sigma[idx] * (Qs[v * N + idx] - qr[s]) * m[REF_M_INVJ * N + idx];
+            }
+        }
+    }
     free(grad);
     free(theta);
     free(phi);
     free(pgrad);
+    free(Qb);
     return bad ? 1 : 0;
 }
 
@@ -1172,6 +1530,7 @@ int ref_rhs(const ref_cfg *g, const double *m, const double *Q, double *res)
 /* ------------------------------------------------------------------------ */
 int ref_diagnostics(const ref_cfg *g, const double *m, const double *Q, double *fields, double *integrals)
 {
+    if (any_bounded(g)) return -2;
     const long N = ncell_of(g);
     double *grad = (double *)calloc((size_t)12 * N, sizeof(double));
     double *rgrad = (double *)calloc((size_t)3 * N, sizeof(double));
@@ -1244,6 +1603,9 @@ double ref_cfl_min(const ref_cfg *g, const double *m, const double *Q)
     const long N = ncell_of(g);
     double best = INFINITY, bestv = INFINITY;
     for (long idx = 0; idx < N; ++idx) {
+        int ijk[3];
+        unpack(g, idx, ijk);
+        if (!in_interior(g, ijk)) continue;  /* ghost cells are not advanced */
         prim_t s = primitive(g, Q, idx);
         double c = sqrt(g->gamma * s.p / s.r);
         double nu = g->viscous ? viscosity(g, s.T) / s.r : 0.0;
@@ -1276,6 +1638,9 @@ void ref_rk_stage(const ref_cfg *g, const double *m, int stage, double dt,
     const int nv = g->ndim + 2;
     for (int v = 0; v < nv; ++v)
         for (long idx = 0; idx < N; ++idx) {
+            int ijk[3];
+            unpack(g, idx, ijk);
+            if (!in_interior(g, ijk)) continue;  /* ghost cells are not advanced */
             long e = v * N + idx;
             double L = m[REF_M_J * N + idx] * (res[e] - m[REF_M_INVJT * N + idx] * Q[e]);
             Q[e] = A[stage] * Qn[e] + B[stage] * (Q[e] + dt * L);
@@ -1301,6 +1666,7 @@ int ref_step(const ref_cfg *g, double *m, const double *xyz, const double *xyz_t
         rc = ref_rhs(g, m, Q, res);
         if (!rc) ref_rk_stage(g, m, s, dt, Qn, Q, res);
     }
+    if (!rc && any_bounded(g)) ref_apply_bc(g, m, Q);  /* ghost cells of the new state */
     free(Qn);
     free(res);
     if (dt_out) *dt_out = dt;

@@ -9,8 +9,9 @@
  *
  * Layout: every field is a structure-of-arrays block [var][nk][nj][ni], i
  * fastest. Direction d = 0, 1, 2 is xi, eta, zeta; coordinate c = 0, 1, 2 is
- * x, y, z. All grids are periodic in every direction; ``off[d][c]`` is the
- * shift of coordinate c when the index along d wraps once.
+ * x, y, z. A periodic direction has ``off[d][c]``, the shift of coordinate
+ * c when the index along d wraps once; a non-periodic one carries ghost
+ * layers (see ref_cfg.bc).
  *
  * Parity pins and their status are listed per function in gbr_oracle.c.
  */
@@ -24,6 +25,11 @@ extern "C" {
 enum { REF_LIM_NONE = 0, REF_LIM_MP = 1, REF_LIM_DUCROS = 2 };
 enum { REF_SCHEME_MEG6 = 0, REF_SCHEME_MIG4 = 1 };
 enum { REF_DT_CFL = 0, REF_DT_FIXED = 1 };
+/* Boundary types per direction and side (Sec. 6): periodic (both sides of a
+ * direction), Dirichlet inflow (ghost cells keep the state stored in them),
+ * zero-gradient outflow, reflecting slip wall.                            */
+enum { REF_BC_PERIODIC = 0, REF_BC_INFLOW = 1, REF_BC_OUTFLOW = 2, REF_BC_WALL = 3 };
+#define REF_NG 6  /* ghost layers on each non-periodic side */
 
 typedef struct {
     int n[3];          /* cells along xi, eta, zeta                          */
@@ -37,6 +43,11 @@ typedef struct {
     double theta_c;    /* shock-sensor threshold                             */
     double alpha_mp, beta_mp; /* MP limiter constants                      */
     double alpha_d;    /* alpha-damping coefficient                          */
+    /* Non-periodic directions: n[d] counts REF_NG ghost layers on each side
+     * (interior cells REF_NG .. n[d] - REF_NG - 1). Static MEG6 grids only. */
+    int bc[3][2];      /* REF_BC_* per direction, side 0 (low) and 1 (high)  */
+    const double *sigma; /* sponge strength per cell, or NULL                */
+    double qref[5];    /* sponge reference state (rho, u, v, w, p)           */
 } ref_cfg;
 
 /* Metric block: one contiguous array of REF_M_TOTAL * ncell doubles. Slot s
@@ -68,6 +79,13 @@ int ref_line_ig4(const double *v, int n, double shift, double *out);
 int ref_line_ig4_face(const double *v, int n, double shift, double *out);
 int ref_line_ig4_dcomp(const double *v, int n, double shift, double *out);
 
+/* App. C on a non-periodic line of m >= 12 interior values: first and
+ * second derivatives with the boundary closures (p, h: m values each) and
+ * the interface values F[0..m] (F[f] between cells f - 1 and f). Return -1
+ * if m < 12.                                                              */
+int ref_bline_derivs(const double *v, int m, double *p, double *h);
+int ref_bline_faces(const double *v, int m, double *F);
+
 /* --- pointwise pieces --------------------------------------------------- */
 void ref_eigvec(const double nrm[3], double rho, double a, double R[25], double Rinv[25]);
 double ref_mp_limit(double wm1, double w0, double wp1, double dm1, double d0,
@@ -77,6 +95,8 @@ void ref_hllc(const double PL[5], const double PR[5], const double nt_n[4],
 void ref_euler_flux(const double P[5], const double nt_n[4], double gamma, double F[5]);
 
 /* --- whole-grid operations ---------------------------------------------- */
+/* Ghost cells of Q from the boundary types (Sec. 6), directions in order. */
+void ref_apply_bc(const ref_cfg *cfg, const double *m, double *Q);
 int ref_metrics(const ref_cfg *cfg, const double *xyz, const double *xyz_t, double *m);
 int ref_metrics_nonfp(const ref_cfg *cfg, const double *xyz, double *m);
 void ref_gradients(const ref_cfg *cfg, const double *Q, double *grad);

@@ -17,6 +17,8 @@ Conventions
     ``xyz_t``: float64 [3][nk][nj][ni] grid velocity at the cell centres, or
                None for a static grid.
   In 2-D the z coordinate is zero and ``off[2] = (0, 0, 1)``.
+    ``bc``   : optional, per direction a pair (low, high) of "periodic",
+               "inflow", "outflow" or "wall" (see ``bounded``).
 * Cell centres are the centroids of the cell's vertices (Sec. 3 of the paper:
   the solution lives at the vertex centroid of each hexahedral cell).
 * Q is float64 [nvar][nk][nj][ni], nvar = ndim + 2, variable order
@@ -380,3 +382,49 @@ def batch2d(count=256, seed=4, log2_min=5.0, log2_max=9.0, L=10.0):
             Q = vortex_sod(g)
         out.append((g, Q, "vortex" if vortex else "sod"))
     return out
+
+
+# ----------------------------------------------------------------------------
+# non-periodic boundaries
+# ----------------------------------------------------------------------------
+NG = 6  # ghost layers on each non-periodic side
+
+
+def bounded(grid, bc):
+    """A copy of ``grid`` with boundary types ``bc`` (per direction a pair
+    (low, high); both "periodic" or both non-periodic). Along a non-periodic
+    direction the first and last NG cells are ghost cells: their
+    coordinates are ignored and their states are set from the boundary type
+    (an "inflow" ghost keeps the state stored in it)."""
+    g = dict(grid)
+    bc = [tuple(b) for b in bc] + [("periodic", "periodic")] * (3 - len(bc))
+    for d, (lo, hi) in enumerate(bc):
+        if (lo == "periodic") != (hi == "periodic"):
+            raise ValueError("a direction is periodic on both sides or on neither")
+        if lo != "periodic" and (d >= grid["ndim"] or grid["n"][d] - 2 * NG < 12):
+            raise ValueError("a non-periodic direction needs at least 12 interior cells")
+    g["bc"] = bc
+    return g
+
+
+def sponge_sigma(grid, width=10, amp=2.0, power=2.0, sides=None):
+    """Sponge strength per cell [nk][nj][ni]: amp * (s / width) ** power in
+    the ``width`` interior cells next to each listed non-periodic side (s =
+    1 .. width, counted from the innermost cell of the layer), zero elsewhere
+    and in ghost cells (the profile shape follows Bodony's layers; only its
+    values enter the solver). ``sides``: (direction, side) pairs, default
+    every non-periodic side."""
+    nk, nj, ni = grid["xyz"].shape[1:]
+    bc = grid.get("bc") or []
+    if sides is None:
+        sides = [(d, s) for d in range(len(bc)) for s in range(2) if bc[d][0] != "periodic"]
+    sig = np.zeros((nk, nj, ni))
+    idx = np.meshgrid(np.arange(nk), np.arange(nj), np.arange(ni), indexing="ij")
+    for d, side in sides:
+        pos = idx[2 - d]
+        n = grid["n"][d]
+        depth = (pos - NG) if side == 0 else (n - NG - 1 - pos)  # 0 at the boundary cell
+        s = width - depth
+        prof = np.where((depth >= 0) & (s > 0), amp * (np.clip(s, 0, None) / width) ** power, 0.0)
+        sig = np.maximum(sig, prof)
+    return sig
