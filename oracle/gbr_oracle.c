@@ -504,6 +504,8 @@ typedef struct {
     const double *src;  /* periodic field (interpolation jobs)             */
     double *out;        /* per-cell result                                 */
     int faces;          /* 0: D_d of fac * x, 1: interface values of src   */
+    const double *org;  /* derivative jobs on bounded grids: per-cell origin
+                         * subtracted from x (NULL: none)                  */
 } line_job;
 
 static int line_job_fn(void *ctx, const long *cells)
@@ -544,7 +546,7 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
     /* Step 1: coordinate derivatives D_d(x_c). */
     for (int d = 0; d < 3 && !rc; ++d)
         for (int c = 0; c < 3 && !rc; ++c) {
-            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0};
+            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0, NULL};
             rc = run_job(jb);
         }
     /* Step 2: hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2]; the product
@@ -553,8 +555,8 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
         int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3 && !rc; ++c) {
             int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0};
-            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0};
+            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0, NULL};
+            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0, NULL};
             rc = run_job(ja);
             if (!rc) rc = run_job(jc);
             if (!rc)
@@ -598,7 +600,7 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
         for (int e = 0; e < 3; ++e)
             for (int c = 0; c < 3; ++c) { src[q] = REF_M_UNHAT(e, c); dst[q++] = REF_M_FUNHAT(f, e, c); }
         for (q = 0; q < 13 && !rc; ++q) {
-            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1};
+            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1, NULL};
             rc = run_job(jb);
         }
     }
@@ -759,22 +761,37 @@ static int bjob_fn(void *ctx, const long *cells)
             J[k] = a * jb->jump;
         }
     }
-    if (!rc && !is_bounded(g, jb->d)) {
-        for (int k = 0; k < n; ++k) {
-            double up = pline_face_at(F, jb->faces ? NULL : J, n, k);
-            jb->out[cells[k]] = jb->faces ? up : up - pline_face_at(F, J, n, k - 1);
+    /* Derivative jobs measure x from the target cell's own coordinate: the
+     * metrics are invariant under a translation (the shift multiplies
+     * D_d2 D_d1 - D_d1 D_d2 of a coordinate, zero because the operators along
+     * different directions commute, App. C rows included), and this keeps
+     * round-off at O(eps) on strongly stretched grids. */
+    double *G = (double *)calloc((size_t)n + 1, sizeof(double));
+    if (!G) rc = -1;
+    const int bnd = is_bounded(g, jb->d);
+    const int m = n - 2 * REF_NG;
+    for (int k = 0; k < n && !rc; ++k) {
+        if (bnd && (k < REF_NG || k >= n - REF_NG) && !jb->faces) continue;
+        const double *V = F;
+        if (!jb->faces && jb->org) {
+            const double o = jb->org[cells[k]];
+            for (int q = 0; q < n; ++q) G[q] = (jb->fac ? jb->fac[cells[q]] : 1.0) * (jb->xc[cells[q]] - o);
+            V = G;
         }
-    } else if (!rc) {
-        const int m = n - 2 * REF_NG;
-        rc = ref_bline_faces(F + REF_NG, m, f);
-        if (!rc) {
-            if (jb->faces)
-                for (int q = 0; q <= m; ++q) jb->out[cells[REF_NG - 1 + q]] = f[q];
-            else
-                for (int k = 0; k < m; ++k) jb->out[cells[REF_NG + k]] = f[k + 1] - f[k];
+        if (!bnd) {
+            double up = pline_face_at(V, jb->faces ? NULL : J, n, k);
+            jb->out[cells[k]] = jb->faces ? up : up - pline_face_at(V, J, n, k - 1);
+        } else if (jb->faces) {
+            if (k == 0) {
+                rc = ref_bline_faces(V + REF_NG, m, f);
+                for (int q = 0; q <= m && !rc; ++q) jb->out[cells[REF_NG - 1 + q]] = f[q];
+            }
+        } else {
+            rc = ref_bline_faces(V + REF_NG, m, f);
+            if (!rc) jb->out[cells[k]] = f[k - REF_NG + 1] - f[k - REF_NG];
         }
     }
-    free(F); free(J); free(f);
+    free(F); free(J); free(f); free(G);
     return rc;
 }
 
@@ -799,7 +816,7 @@ static int metrics_bounded(const ref_cfg *g, const double *xyz, const double *xy
     /* Step 1: coordinate derivatives D_d(x_c). */
     for (int d = 0; d < 3 && !rc; ++d)
         for (int c = 0; c < 3 && !rc; ++c) {
-            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0};
+            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0, xyz + c * N};
             rc = run_bjob(jb);
         }
     /* Step 2: hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2]. */
@@ -807,8 +824,8 @@ static int metrics_bounded(const ref_cfg *g, const double *xyz, const double *xy
         int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3 && !rc; ++c) {
             int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0};
-            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0};
+            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0, xyz + c2 * N};
+            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0, xyz + c2 * N};
             rc = run_bjob(ja);
             if (!rc) rc = run_bjob(jc);
             if (!rc)
@@ -848,7 +865,7 @@ static int metrics_bounded(const ref_cfg *g, const double *xyz, const double *xy
         for (int e = 0; e < 3; ++e)
             for (int c = 0; c < 3; ++c) { src[q] = REF_M_UNHAT(e, c); dst[q++] = REF_M_FUNHAT(f, e, c); }
         for (q = 0; q < 13 && !rc; ++q) {
-            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1};
+            line_job jb = {g, f, NULL, NULL, 0.0, m + (long)src[q] * N, m + (long)dst[q] * N, 1, NULL};
             rc = run_bjob(jb);
         }
     }

@@ -144,13 +144,11 @@ def test_bounded_metrics_exact_on_affine_grid():
                   [("inflow", "outflow"), ("wall", "wall")])
     m = oracle.metrics(g)
     inv = np.linalg.inv(A)
-    # bounded lines use the coordinates as given (|x| up to 30 cells): round-off
-    # of the nested products grows to ~2e-13
     for d in range(3):
         for c in range(3):
-            assert np.abs(m[oracle.M_UNHAT(d, c)] - inv[d, c]).max() <= 1e-12
-            assert np.abs(m[oracle.M_FUNHAT(d, d, c)] - inv[d, c]).max() <= 1e-12
-    assert np.abs(m[oracle.M_INVJ] - np.linalg.det(A)).max() <= 1e-12
+            assert np.abs(m[oracle.M_UNHAT(d, c)] - inv[d, c]).max() <= 1e-13
+            assert np.abs(m[oracle.M_FUNHAT(d, d, c)] - inv[d, c]).max() <= 1e-13
+    assert np.abs(m[oracle.M_INVJ] - np.linalg.det(A)).max() <= 1e-13
 
 
 def test_bounded_rejects_unsupported():
@@ -270,9 +268,7 @@ def test_curvilinear_deep_interior_unaffected():
     gb = W.bounded(gp, [("inflow", "inflow")])
     rb = oracle.rhs(gb, oracle.metrics(gb), Q, **params)
     deep = (Ellipsis, slice(NG + 12, 44 - NG - 12))
-    # the two metric paths round differently (lines in the coordinates as
-    # given vs windows about each cell)
-    assert np.abs(rb[deep] - rp[deep]).max() <= 1e-12 * np.abs(rp).max()
+    assert np.abs(rb[deep] - rp[deep]).max() <= 1e-13 * np.abs(rp).max()
     near = (Ellipsis, slice(NG, NG + 3))
     assert np.abs(rb[near] - rp[near]).max() > 1e-8  # App. C metrics differ near the boundary
 
