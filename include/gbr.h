@@ -17,8 +17,12 @@
  *    FP64. Conserved variables in the order (rho, rho u, rho v, [rho w], E):
  *    nvar = ndim + 2. Coordinates are [3][nk][nj][ni] (x, y, z); for ndim = 2
  *    the z plane is ignored and z is taken as the zeta index.
- *  - Every grid is periodic in every direction; off[d] is the (x, y, z)
- *    shift of the coordinates when the index along direction d wraps once.
+ *  - A direction is periodic (off[d] is the (x, y, z) shift of the
+ *    coordinates when the index along d wraps once) or, per bc[d], bounded
+ *    on both sides: then the first and last GBR_NG cells along d are ghost
+ *    cells (Sec. 6). Ghost cells are part of every field array; they are
+ *    not advanced in time, their coordinates are ignored and their states
+ *    follow the boundary type (see GBR_BC_*).
  *  - Work is enqueued on the HIP stream given at creation (or by
  *    gbr_set_stream); calls return without waiting unless stated.
  *  - Batch-first: calls take an array of n >= 0 grid handles and per-grid
@@ -60,6 +64,24 @@ enum { GBR_DT_CFL = 0, GBR_DT_FIXED = 1 };
  * the viscous gradients, the sensor and, as Sec. 7 directs, the metric
  * interpolation.                                                           */
 enum { GBR_SCHEME_MEG6 = 0, GBR_SCHEME_MIG4 = 1 };
+/* Boundary types (Sec. 6) per direction and side of gbr_config.bc:
+ *  GBR_BC_PERIODIC: both sides of the direction (the default, all zero).
+ *  GBR_BC_INFLOW:   Dirichlet; the ghost cells keep the conserved state the
+ *                   caller stores in them (the library never writes them).
+ *  GBR_BC_OUTFLOW:  zero gradient; ghost cells take the state of the
+ *                   boundary cell of their grid line.
+ *  GBR_BC_WALL:     reflecting slip wall; the ghost cell at depth k mirrors
+ *                   the interior cell at depth k with the velocity component
+ *                   along the unit normal of the boundary face reversed.
+ * Directions are filled in order xi, eta, zeta over the full extent of the
+ * others (corner ghosts take the later direction's rule). A bounded
+ * direction needs n[d] >= 2 GBR_NG + 12 and d < ndim. Metrics near the
+ * boundary use the one-sided closures of App. C; interfaces and gradients
+ * of interior cells read up to GBR_NG ghost cells, as the paper notes the
+ * flux formulae stay unchanged at boundaries. Bounded grids are static and
+ * use GBR_SCHEME_MEG6.                                                    */
+enum { GBR_BC_PERIODIC = 0, GBR_BC_INFLOW = 1, GBR_BC_OUTFLOW = 2, GBR_BC_WALL = 3 };
+#define GBR_NG 6
 
 typedef struct gbr_config {
     int32_t ndim;      /* 2 or 3 (n[2] must be 1 when ndim == 2)                  */
@@ -80,6 +102,7 @@ typedef struct gbr_config {
     double alpha_mp;   /* MP limiter alpha (4)                                    */
     double beta_mp;    /* MP limiter beta (4)                                     */
     double alpha_d;    /* alpha-damping coefficient alpha^D (4, Sec. 5.2)         */
+    int32_t bc[3][2];  /* GBR_BC_* per direction, side 0 (low) and 1 (high)      */
 } gbr_config;
 
 typedef struct gbr_grid_s *gbr_grid;
@@ -127,7 +150,15 @@ gbr_status gbr_set_stream(gbr_grid g, void *hip_stream);
  * xyz[b]: cell-centre coordinates of grid b, [3][nk][nj][ni].
  * xyz_t[b]: grid velocity at the cell centres, same layout; required (non
  * NULL) for moving grids, ignored otherwise (xyz_t itself may be NULL).
- * Synchronises the stream and returns GBR_E_JACOBIAN if any 1/J <= 0.       */
+ * On grids with bounded directions the derivatives and interface values
+ * along them use the App. C closures on the interior cells (the first
+ * and second derivatives of the first three cells from the one-sided,
+ * partially one-sided and central formulas; the interface next to the
+ * boundary face from the inward cell; the boundary face from the boundary
+ * cell), and every ghost slot holds the value of the nearest interior cell
+ * (nearest interface from the boundary face inwards for face slots).
+ * Synchronises the stream and returns GBR_E_JACOBIAN if any interior
+ * 1/J <= 0.                                                                 */
 gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz,
                        const double *const *xyz_t);
 
@@ -138,28 +169,35 @@ gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz,
  * entry has a zeta where the cycle has xi), interface values from
  * Eq. interp-formulae with that derivative in place of E6. A uniform flow
  * then does not stay uniform on curved grids (Sec. 8.1.1). Errors as
- * gbr_metrics; GBR_E_UNSUPPORTED for moving grids.                         */
+ * gbr_metrics; GBR_E_UNSUPPORTED for moving or bounded grids.             */
 gbr_status gbr_metrics_nonfp(const gbr_grid *g, int n, const double *const *xyz);
 
 /* Right-hand side Res = d(Q/J)/dt (Sec. 3, Sec. 5.1 Steps 1-7, Sec. 5.2
  * Steps 1-5): res[b] receives -sum_d [Phi(+1/2) - Phi(-1/2)] with
  * Phi = F - F^v, the directions accumulated in the order xi, eta, zeta.
  * Q[b]: conserved state (read only, double). res[b]: output, nvar arrays of
- * double (GBR_FP64) or float (GBR_FP32_BULK); must not alias Q[b]. Asynchronous; a non-physical state (cell or reconstructed
- * interface) sets the grid's state flag, reported by gbr_check_state.      */
+ * double (GBR_FP64) or float (GBR_FP32_BULK); must not alias Q[b].
+ * Bounded grids: ghost primitives come from the boundary types (Q itself
+ * is not written), Res is zero in ghost cells, and a sponge set with
+ * gbr_set_sponge adds -sigma (Q - Q_ref) / J in interior cells.
+ * Asynchronous; a non-physical interior state or reconstructed interface
+ * state of an interior cell sets the grid's state flag, reported by
+ * gbr_check_state.                                                          */
 gbr_status gbr_rhs(const gbr_grid *g, int n, const double *const *Q, void *const *res);
 
 /* One SSP-RK3 stage (App. B with Eq. time-split), in place on Q[b]:
  *   Q <- a_s Qn + b_s (Q + dt J (Res - (1/J)_t Q)),
  * (a_s, b_s) = (0, 1), (3/4, 1/4), (1/3, 2/3) for stage = 0, 1, 2.
  * dt[b]: device pointer to the grid's time step (one double). res[b] has the
- * grid's precision (double or float); the update itself is in double.      */
+ * grid's precision (double or float); the update itself is in double.
+ * Ghost cells of bounded grids are left unchanged.                          */
 gbr_status gbr_rk_stage(const gbr_grid *g, int n, int stage, const double *const *dt,
                         const double *const *Qn, double *const *Q, const void *const *res);
 
 /* Time step (App. B): dt[b] <- cfl * min over cells and directions of
  * 1/(|U| + c |grad d|), and for viscous grids also (1/alpha_d) min
- * 1/(nu |grad d|^2). dt[b] is a device pointer; no host synchronisation.   */
+ * 1/(nu |grad d|^2), over interior cells. dt[b] is a device pointer; no
+ * host synchronisation.                                                     */
 gbr_status gbr_cfl(const gbr_grid *g, int n, const double *const *Q, double cfl,
                    double *const *dt);
 
@@ -168,7 +206,10 @@ gbr_status gbr_cfl(const gbr_grid *g, int n, const double *const *Q, double cfl,
  * time step (dt_mode GBR_DT_CFL: cfl_or_dt is the CFL number; GBR_DT_FIXED:
  * cfl_or_dt is dt), then three RHS evaluations and stages. Qn and Res are
  * library-owned. dt_out[b] (device pointer, may be NULL / the array may be
- * NULL) receives the step's dt. Asynchronous.                               */
+ * NULL) receives the step's dt. Bounded grids advance interior cells only;
+ * each stage sets ghost primitives from the boundary types, and at the end
+ * of the step the outflow and wall ghost cells of Q receive their states
+ * (inflow ghost cells are never written). Asynchronous.                    */
 gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *const *xyz,
                     const double *const *xyz_t, double cfl_or_dt, int dt_mode,
                     double *const *dt_out);
@@ -190,9 +231,20 @@ gbr_status gbr_check_state(gbr_grid g);
  *   rho |u|^2 / 2 and rho |curl u|^2 / 2, and the volume sum of 1/J.
  * Cell volumes are 1/J; the sums are taken in a fixed order, so repeated
  * calls give identical results. Uses the grid's gradient scratch (not
- * concurrently with gbr_rhs / gbr_step on the same grid). Asynchronous.    */
+ * concurrently with gbr_rhs / gbr_step on the same grid). Asynchronous.
+ * GBR_E_UNSUPPORTED on bounded grids.                                       */
 gbr_status gbr_diagnostics(const gbr_grid *g, int n, const double *const *Q, double *const *fields,
                            double *const *integrals);
+
+/* Sponge layers (Sec. 8.3, after Bodony): the right-hand side gains the
+ * relaxation source -sigma (Q - Q_ref), i.e. Res += -sigma (Q - Q_ref) / J,
+ * in interior cells. sigma: device pointer to ncell doubles (>= 0; zero
+ * outside the layers), copied into library memory on g's stream before the
+ * call returns (the caller may free it afterwards). ref: host pointer to
+ * the reference primitive state (rho, u, v, w, p); w is ignored in 2-D.
+ * sigma == NULL removes the sponge. Errors: GBR_E_ARG (null g, null ref
+ * with non-null sigma, rho or p <= 0), GBR_E_NOMEM, GBR_E_DEVICE.          */
+gbr_status gbr_set_sponge(gbr_grid g, const double *sigma, const double *ref);
 
 /* Read-only device pointer to one metric slot (GBR_SLOT_*), ncell doubles,
  * owned by the library; NULL on a bad slot. Valid until gbr_grid_destroy.  */
@@ -237,8 +289,8 @@ typedef struct gbr_batch_s *gbr_batch;
 enum { GBR_TILE_AUTO = -1, GBR_TILE_16X16 = 0, GBR_TILE_32X8 = 1, GBR_TILE_8X32 = 2, GBR_TILE_COUNT = 3 };
 
 /* Bind n >= 1 grids and their states for batched stepping.
- * Every grid must be 2-D, inviscid, static, MEG6, with limiter GBR_LIM_NONE
- * or GBR_LIM_MP, and all must share precision, limiter, gamma, the MP
+ * Every grid must be 2-D, inviscid, static, periodic, MEG6, without a
+ * sponge, with limiter GBR_LIM_NONE or GBR_LIM_MP, and all must share precision, limiter, gamma, the MP
  * constants, the stream and the device; a grid may appear once. Metrics
  * must be computed (gbr_metrics) before gbr_batch_run.
  * Q[b]: device state of grid b, advanced in place by gbr_batch_run; it must

@@ -12,7 +12,12 @@ namespace gbr {
 Dims dims_of(const gbr_grid_s *g)
 {
     Dims d;
-    for (int q = 0; q < 3; ++q) d.n[q] = g->cfg.n[q];
+    for (int q = 0; q < 3; ++q) {
+        d.n[q] = g->cfg.n[q];
+        const bool b = g->cfg.bc[q][0] != GBR_BC_PERIODIC;
+        d.lo[q] = b ? kNg : 0;
+        d.hi[q] = b ? d.n[q] - kNg : d.n[q];
+    }
     d.ncell = g->ncell;
     return d;
 }
@@ -87,7 +92,23 @@ bool config_ok(const gbr_config *c, const char **why)
     if (c->scheme != GBR_SCHEME_MEG6 && c->scheme != GBR_SCHEME_MIG4) return *why = "unknown scheme", false;
     if (!(c->gamma > 1.0) || !(c->Re > 0.0) || !(c->Pr > 0.0) || !(c->Mref > 0.0) || !(c->suth >= 0.0))
         return *why = "gamma must exceed 1 and Re, Pr, Mref be positive", false;
+    for (int d = 0; d < 3; ++d) {
+        for (int side = 0; side < 2; ++side)
+            if (c->bc[d][side] < GBR_BC_PERIODIC || c->bc[d][side] > GBR_BC_WALL)
+                return *why = "unknown boundary type", false;
+        const bool lo = c->bc[d][0] != GBR_BC_PERIODIC, hi = c->bc[d][1] != GBR_BC_PERIODIC;
+        if (lo != hi) return *why = "a direction is periodic on both sides or on neither", false;
+        if (lo && (d >= c->ndim || c->n[d] < 2 * GBR_NG + 12))
+            return *why = "a bounded direction needs d < ndim and n[d] >= 2 GBR_NG + 12", false;
+    }
     return true;
+}
+
+bool any_bounded(const gbr_config *c)
+{
+    for (int d = 0; d < 3; ++d)
+        if (c->bc[d][0] != GBR_BC_PERIODIC) return true;
+    return false;
 }
 
 size_t bytes_for(const gbr_config *c)
@@ -131,7 +152,7 @@ void release(gbr_grid_s *g)
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
     for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->grad2, (void *)g->prim,
-                    (void *)g->prim2,
+                    (void *)g->prim2, (void *)g->sigma,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
@@ -164,9 +185,13 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     *out = nullptr;
     const char *why = nullptr;
     if (!config_ok(cfg, &why)) return GBR_E_ARG;
+    // App. C covers static grids; the IG4 line system has no boundary closure
+    // in the paper
+    if (any_bounded(cfg) && (cfg->moving || cfg->scheme != GBR_SCHEME_MEG6)) return GBR_E_UNSUPPORTED;
     gbr_grid_s *g = new (std::nothrow) gbr_grid_s;
     if (!g) return GBR_E_NOMEM;
     g->cfg = *cfg;
+    g->bounded = any_bounded(cfg);
     g->stream = (hipStream_t)hip_stream;
     g->ncell = (long)cfg->n[0] * cfg->n[1] * cfg->n[2];
     g->nvar = cfg->ndim + 2;
@@ -226,7 +251,7 @@ gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz, const
         const double *xt = xyz_t ? xyz_t[b] : nullptr;
         if (gg->cfg.moving && !xt) return fail(gg, GBR_E_ARG, "moving grid needs grid velocities");
         hipError_t e = hipMemsetAsync(gg->flags + 1, 0, sizeof(int), gg->stream);
-        if (e == hipSuccess) e = gbr::launch_metrics(gg, xyz[b], xt);
+        if (e == hipSuccess) e = gg->bounded ? gbr::launch_metrics_bounded(gg, xyz[b]) : gbr::launch_metrics(gg, xyz[b], xt);
         if (e != hipSuccess) return hip_fail(gg, e, "metrics launch");
     }
     for (int b = 0; b < n; ++b) {
@@ -250,6 +275,7 @@ gbr_status gbr_metrics_nonfp(const gbr_grid *g, int n, const double *const *xyz)
         gbr_grid_s *gg = g[b];
         if (!xyz[b]) return fail(gg, GBR_E_ARG, "null coordinates");
         if (gg->cfg.moving) return fail(gg, GBR_E_UNSUPPORTED, "non-conservative metrics are for static grids");
+        if (gg->bounded) return fail(gg, GBR_E_UNSUPPORTED, "non-conservative metrics are for periodic grids");
         hipError_t e = hipMemsetAsync(gg->flags + 1, 0, sizeof(int), gg->stream);
         if (e == hipSuccess) e = gbr::launch_metrics_nonfp(gg, xyz[b]);
         if (e != hipSuccess) return hip_fail(gg, e, "metrics launch");
@@ -337,6 +363,7 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
                 e = gbr::launch_fill(gg, gg->dt, 1, cfl_or_dt);
         }
         for (int st = 0; st < 3 && e == hipSuccess; ++st) e = gbr::launch_step_stage(gg, st, gg->dt, Q[b], gg->qn);
+        if (e == hipSuccess && gg->bounded) e = gbr::launch_bc_state(gg, Q[b]);
         if (e == hipSuccess && dt_out && dt_out[b]) e = gbr::launch_copy(gg, dt_out[b], gg->dt, 1);
         if (e != hipSuccess) return hip_fail(gg, e, "step launch");
     }
@@ -352,6 +379,7 @@ gbr_status gbr_diagnostics(const gbr_grid *g, int n, const double *const *Q, dou
     if (!Q) return fail(g[0], GBR_E_ARG, "null state array");
     for (int b = 0; b < n; ++b) {
         if (!Q[b]) return fail(g[b], GBR_E_ARG, "null state");
+        if (g[b]->bounded) return fail(g[b], GBR_E_UNSUPPORTED, "diagnostics are for periodic grids");
         hipError_t e = gbr::launch_diagnostics(g[b], Q[b], fields ? fields[b] : nullptr,
                                                integrals ? integrals[b] : nullptr);
         if (e != hipSuccess) return hip_fail(g[b], e, "diagnostics launch");
@@ -370,6 +398,33 @@ gbr_status gbr_check_state(gbr_grid g)
     if (e != hipSuccess) return hip_fail(g, e, "state check");
     if (flags[1]) return fail(g, GBR_E_JACOBIAN, "non-positive Jacobian in a metric update");
     if (flags[0]) return fail(g, GBR_E_STATE, "non-physical state (rho <= 0, p <= 0 or non-finite)");
+    return GBR_OK;
+}
+
+gbr_status gbr_set_sponge(gbr_grid g, const double *sigma, const double *ref)
+{
+    if (!g) return GBR_E_ARG;
+    if (!sigma) {
+        hipError_t e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "sponge sync");
+        if (g->sigma) (void)hipFree(g->sigma);
+        g->sigma = nullptr;
+        return GBR_OK;
+    }
+    if (!ref) return fail(g, GBR_E_ARG, "null sponge reference state");
+    if (!(ref[0] > 0.0) || !(ref[4] > 0.0)) return fail(g, GBR_E_ARG, "sponge reference needs rho, p > 0");
+    hipError_t e = hipSuccess;
+    if (!g->sigma) e = hipMalloc((void **)&g->sigma, (size_t)g->ncell * sizeof(double));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->sigma, sigma, (size_t)g->ncell * sizeof(double), hipMemcpyDeviceToDevice, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "sponge copy");
+    const double w = g->cfg.ndim == 3 ? ref[3] : 0.0;
+    g->qref[0] = ref[0];
+    g->qref[1] = ref[0] * ref[1];
+    g->qref[2] = ref[0] * ref[2];
+    g->qref[3] = ref[0] * w;
+    g->qref[4] = ref[4] / (g->cfg.gamma - 1.0) + 0.5 * ref[0] * (ref[1] * ref[1] + ref[2] * ref[2] + w * w);
     return GBR_OK;
 }
 

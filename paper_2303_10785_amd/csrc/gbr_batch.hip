@@ -495,9 +495,10 @@ gbr_status gbr_batch_create(const gbr_grid *g, int n, double *const *Q, int tile
     for (int b = 0; b < n; ++b) {
         const gbr_config &c = g[b]->cfg;
         if (!Q[b]) return g0->err = "null state", GBR_E_ARG;
-        if (c.ndim != 2 || c.viscous || c.moving || c.scheme != GBR_SCHEME_MEG6 ||
+        if (c.ndim != 2 || c.viscous || c.moving || c.scheme != GBR_SCHEME_MEG6 || g[b]->bounded || g[b]->sigma ||
             (c.limiter != GBR_LIM_NONE && c.limiter != GBR_LIM_MP))
-            return g0->err = "batched stepping needs static 2-D Euler MEG6 grids with limiter NONE or MP",
+            return g0->err = "batched stepping needs static periodic 2-D Euler MEG6 grids without a sponge, "
+                             "with limiter NONE or MP",
                    GBR_E_UNSUPPORTED;
         const gbr_config &c0 = g0->cfg;
         if (c.precision != c0.precision || c.limiter != c0.limiter || c.gamma != c0.gamma ||

@@ -27,6 +27,9 @@ struct gbr_grid_s {
     double *dt = nullptr;        // 1: time step of the last gbr_step / gbr_cfl
     unsigned long long *dtmin = nullptr;  // 1: min-reduction word (bit pattern of a positive double)
     int *flags = nullptr;        // [0] non-physical state, [1] non-positive Jacobian
+    double *sigma = nullptr;     // ncell: sponge strength (gbr_set_sponge), or null
+    double qref[5] = {0, 0, 0, 0, 0};  // sponge reference state, conserved
+    bool bounded = false;        // some direction is non-periodic
     std::string err;
     // kernel timing (gbr_timing_enable): event pairs per launch
     bool timing = false;
@@ -39,11 +42,30 @@ namespace gbr {
 
 constexpr int kReducePartials = 4096;
 
-// Dimensions and physics parameters passed by value to kernels.
+// Ghost layers on each side of a non-periodic direction.
+constexpr int kNg = GBR_NG;
+
+// Dimensions and physics parameters passed by value to kernels. Cells with
+// lo[d] <= index < hi[d] along every d are interior (advanced in time);
+// lo = 0, hi = n along periodic directions.
 struct Dims {
     int n[3];
     long ncell;
+    int lo[3], hi[3];
 };
+
+__host__ __device__ inline bool in_box(const Dims &dm, int i, int j, int k)
+{
+    return i >= dm.lo[0] && i < dm.hi[0] && j >= dm.lo[1] && j < dm.hi[1] && k >= dm.lo[2] && k < dm.hi[2];
+}
+
+__host__ __device__ inline bool in_box(const Dims &dm, long idx)
+{
+    const int i = int(idx % dm.n[0]);
+    const int j = int((idx / dm.n[0]) % dm.n[1]);
+    const int k = int(idx / ((long)dm.n[0] * dm.n[1]));
+    return in_box(dm, i, j, k);
+}
 
 struct Phys {
     double gamma;
@@ -103,6 +125,18 @@ hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, do
 // Q: state at the start of the step, advanced in place; S: stage buffer.
 hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
+// Non-periodic boundaries (gbr_bounds.hip): App. C metrics of a static grid
+// with ghost slots copied from the nearest interior ones; ghost primitives
+// from the boundary types (Dirichlet ghosts from Q's own ghost cells); ghost
+// states of Q after a step; ghost sensor values; sponge term added to Res.
+hipError_t launch_metrics_bounded(gbr_grid_s *g, const double *xyz);
+template <class R>
+hipError_t launch_bc_prims(gbr_grid_s *g, R *prim, const double *Q);
+hipError_t launch_bc_state(gbr_grid_s *g, double *Q);
+template <class R>
+hipError_t launch_theta_ghosts(gbr_grid_s *g, R *theta);
+template <class R>
+hipError_t launch_sponge(gbr_grid_s *g, const double *Q, R *res);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);
 

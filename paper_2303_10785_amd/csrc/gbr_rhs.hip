@@ -68,6 +68,8 @@ struct RhsArgs {
     const double *dt;  // time step (device)
     double ca, cb;     // stage coefficients
     R *prim_out;       // primitives of the updated state for the next stage, or null
+    const double *sigma;  // sponge strength per cell (fused stage), or null
+    double qref[5];       // sponge reference state, conserved
 };
 
 __device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
@@ -108,7 +110,10 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
     a.prim[3 * N + idx] = R(w);
     a.prim[4 * N + idx] = R(p);
     a.prim[5 * N + idx] = R(T);
-    if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)))
+    // ghost cells of bounded directions take their states from the boundary
+    // types afterwards; only interior states are checked
+    if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)) &&
+        in_box(a.dm, idx))
         atomicOr(a.flags, 1);
 }
 
@@ -539,7 +544,16 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
         phi[4] -= nx * bx + ny * by + nz * bz;
     }
     ok = ok && isfinite(phi[0]) && isfinite(phi[4]);
-    if (!ok && cg < nc) atomicOr(a.flags, 1);
+    if (!ok && cg < nc) {
+        // only interfaces of interior cells count (ghost interfaces of
+        // bounded directions are computed but never used)
+        int lo3[3], hi3[3];
+        lo3[T::SD] = s0 + t - 1;
+        hi3[T::SD] = s0 + t;
+        lo3[T::CD] = hi3[T::CD] = cg;
+        lo3[3 - T::SD - T::CD] = hi3[3 - T::SD - T::CD] = o;
+        if (in_box(dm, lo3[0], lo3[1], lo3[2]) || in_box(dm, hi3[0], hi3[1], hi3[2])) atomicOr(a.flags, 1);
+    }
     __syncthreads();
     // interface fluxes back to LDS (reusing the primitive buffer)
 #pragma unroll
@@ -549,14 +563,23 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     // with t and the cross lane of this thread's home position
     const int th = T::t_of(tid), clh = T::c_of(tid);
     const int cgh = c0 + clh;
-    if (th < TS - 1 && s0 + th < ns && cgh < nc) {
+    int h3[3];
+    h3[T::SD] = s0 + th;
+    h3[T::CD] = cgh;
+    h3[3 - T::SD - T::CD] = o;
+    const bool interior = in_box(dm, h3[0], h3[1], h3[2]);
+    if (th < TS - 1 && s0 + th < ns && cgh < nc && (interior || MODE == 0)) {
         const long ch = cell_of(dm, T::SD, T::CD, s0 + th, cgh, o);
         double qnew[5];
-        double dt = 0.0, J = 0.0, it = 0.0;
+        double dt = 0.0, J = 0.0, it = 0.0, sg = 0.0, vj = 0.0;
         if (MODE == 2) {
             dt = *a.dt;
             J = a.m[GBR_SLOT_CELL_J * N + ch];
             it = a.m[GBR_SLOT_CELL_INVJT * N + ch];
+            if (a.sigma) {
+                sg = a.sigma[ch];
+                vj = a.m[GBR_SLOT_CELL_INVJ * N + ch];
+            }
         }
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -565,15 +588,18 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
             const R d = sP[v * kBlock + T::at(th + 1, clh, TS)] - sP[v * kBlock + T::at(th, clh, TS)];
             R *r = a.res + (long)ov * N + ch;
             if (MODE == 0) {
-                *r = -d;
+                *r = interior ? -d : R(0);  // Res is zero in ghost cells
             } else if (MODE == 1) {
                 *r = *r - d;
             } else {
-                // App. B with Eq. time-split: Q <- a Qn + b (Q + dt J (Res - (1/J)_t Q))
+                // App. B with Eq. time-split: Q <- a Qn + b (Q + dt J (Res - (1/J)_t Q)),
+                // Res with the sponge term -sigma (Q - Q_ref) / J (Sec. 8.3)
                 const R res = *r - d;
                 const long e = (long)ov * N + ch;
                 const double q = a.Qin[e];
-                const double L = J * (double(res) - it * q);
+                double rt = double(res);
+                if (a.sigma) rt -= sg * (q - a.qref[v]) * vj;
+                const double L = J * (rt - it * q);
                 qnew[ov] = a.ca * a.Qn[e] + a.cb * (q + dt * L);
                 a.Qout[e] = qnew[ov];
             }
@@ -603,7 +629,7 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
 // SSP-RK3 stage (double accumulation) and time step
 // ----------------------------------------------------------------------------
 template <int NV, class R>
-__global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, double cb,
+__global__ void __launch_bounds__(kBlock) k_rk_stage(Dims dm, long ncell, double ca, double cb,
                                                        const double *__restrict__ dtp,
                                                        const double *__restrict__ Qn,
                                                        double *__restrict__ Q,
@@ -612,7 +638,7 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(long ncell, double ca, doub
                                                        const double *__restrict__ invjt)
 {
     long c = blockIdx.x * (long)kBlock + threadIdx.x;
-    if (c >= ncell) return;
+    if (c >= ncell || !in_box(dm, c)) return;  // ghost cells are not advanced
     const double dt = *dtp;
     const double J = jac[c], it = invjt[c];
 #pragma unroll
@@ -632,6 +658,7 @@ __global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const 
     const long N = dm.ncell;
     double best = __builtin_inf();
     for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
+        if (!in_box(dm, idx)) continue;  // ghost cells are not advanced
         best = fmin(best, cell_dt_bound<NDIM, VISC>(Q, m, N, idx, ph.gamma, ph.gm1, ph.gM2, ph.suth, ph.re,
                                                         ph.alpha_d));
     }
@@ -820,6 +847,9 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
         Timed timed(g, GBR_K_PRIMS);
         hipLaunchKernelGGL((k_prims<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     }
+    // ghost primitives of bounded directions (Sec. 6); Dirichlet ghosts from
+    // the caller's state a.Q, which the stages never write in ghost cells
+    if (g->bounded && (e = launch_bc_prims<R>(g, a.prim, a.Q)) != hipSuccess) return e;
     if (g->cfg.scheme == GBR_SCHEME_MIG4) {
         // IG4 gradients of all primitives along every direction (they feed the
         // reconstruction as well), then the sensor from them
@@ -849,9 +879,13 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
             hipLaunchKernelGGL((k_cell_grad<NDIM, false, R>), gg, dim3(kBlock), 0, g->stream, a);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (g->bounded && a.pr.limiter == GBR_LIM_DUCROS && (e = launch_theta_ghosts<R>(g, a.theta)) != hipSuccess)
+        return e;
     if ((e = sweep<0, NDIM, VISC, R, false>(g, a)) != hipSuccess) return e;
     if ((e = sweep<1, NDIM, VISC, R, false>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
-    if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, false>(g, a, fuse_rk);
+    if (NDIM == 3 && (e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, false>(g, a, fuse_rk)) != hipSuccess) return e;
+    // the sponge of a plain RHS (the fused stage applies it itself)
+    if (!fuse_rk && g->sigma) e = launch_sponge<R>(g, a.Q, a.res);
     return e;
 }
 
@@ -878,6 +912,8 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.dt = nullptr;
     a.ca = a.cb = 0.0;
     a.prim_out = nullptr;
+    a.sigma = g->sigma;
+    for (int v = 0; v < 5; ++v) a.qref[v] = g->qref[v];
     return a;
 }
 
@@ -974,12 +1010,13 @@ hipError_t rk_typed(gbr_grid_s *g, int stage, const double *dt, const double *Qn
     const double *jac = g->metrics + (long)GBR_SLOT_CELL_J * g->ncell;
     const double *ijt = g->metrics + (long)GBR_SLOT_CELL_INVJT * g->ncell;
     Timed timed(g, GBR_K_RK_STAGE);
+    const Dims dm = dims_of(g);
     if (g->nvar == 5)
-        hipLaunchKernelGGL((k_rk_stage<5, R>), grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage], dt,
-                           Qn, Q, res, jac, ijt);
+        hipLaunchKernelGGL((k_rk_stage<5, R>), grid, dim3(kBlock), 0, g->stream, dm, g->ncell, A[stage], B[stage],
+                           dt, Qn, Q, res, jac, ijt);
     else
-        hipLaunchKernelGGL((k_rk_stage<4, R>), grid, dim3(kBlock), 0, g->stream, g->ncell, A[stage], B[stage], dt,
-                           Qn, Q, res, jac, ijt);
+        hipLaunchKernelGGL((k_rk_stage<4, R>), grid, dim3(kBlock), 0, g->stream, dm, g->ncell, A[stage], B[stage],
+                           dt, Qn, Q, res, jac, ijt);
     return hipGetLastError();
 }
 

@@ -23,6 +23,9 @@ PRECISION = {"fp64": GBR_FP64, "fp32_bulk": GBR_FP32_BULK}
 GBR_SCHEME_MEG6, GBR_SCHEME_MIG4 = 0, 1
 SCHEME = {"meg6": GBR_SCHEME_MEG6, "mig4": GBR_SCHEME_MIG4}
 GBR_DT_CFL, GBR_DT_FIXED = 0, 1
+GBR_BC_PERIODIC, GBR_BC_INFLOW, GBR_BC_OUTFLOW, GBR_BC_WALL = 0, 1, 2, 3
+BC = {"periodic": GBR_BC_PERIODIC, "inflow": GBR_BC_INFLOW, "outflow": GBR_BC_OUTFLOW, "wall": GBR_BC_WALL}
+GBR_NG = 6
 GBR_TILE_AUTO, GBR_TILE_16X16, GBR_TILE_32X8, GBR_TILE_8X32 = -1, 0, 1, 2
 TILE_NAMES = {0: "16x16", 1: "32x8", 2: "8x32"}
 
@@ -86,6 +89,7 @@ class gbr_config(C.Structure):
         ("alpha_mp", C.c_double),
         ("beta_mp", C.c_double),
         ("alpha_d", C.c_double),
+        ("bc", C.c_int32 * 6),
     ]
 
 
@@ -125,6 +129,7 @@ def lib():
     L.gbr_last_error.argtypes = [_VP]
     L.gbr_last_error.restype = C.c_char_p
     L.gbr_metrics_nonfp.argtypes = [_PP, C.c_int, _PP]
+    L.gbr_set_sponge.argtypes = [_VP, _VP, C.POINTER(C.c_double)]
     L.gbr_metrics_nonfp.restype = C.c_int
     L.gbr_diagnostics.argtypes = [_PP, C.c_int, _PP, _PP, _PP]
     L.gbr_diagnostics.restype = C.c_int
@@ -176,7 +181,7 @@ def _check(status, handle=None):
 
 def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1.4, Pr=0.71,
                 Re=1e4, Mref=1.0, suth=110.4 / 293.0, theta_c=0.5, alpha_mp=4.0, beta_mp=4.0,
-                alpha_d=4.0, precision="fp64", scheme="meg6"):
+                alpha_d=4.0, precision="fp64", scheme="meg6", bc=None):
     c = gbr_config()
     c.ndim = int(ndim)
     for d in range(3):
@@ -191,6 +196,10 @@ def make_config(n, ndim, off, viscous=False, limiter="mp", moving=False, gamma=1
         c.off[q] = flat[q]
     c.gamma, c.Pr, c.Re, c.Mref, c.suth = gamma, Pr, Re, Mref, suth
     c.theta_c, c.alpha_mp, c.beta_mp, c.alpha_d = theta_c, alpha_mp, beta_mp, alpha_d
+    for d in range(3):
+        for side in range(2):
+            t = bc[d][side] if bc is not None and d < len(bc) else "periodic"
+            c.bc[d * 2 + side] = BC[t] if isinstance(t, str) else int(t)
     return c
 
 
@@ -226,6 +235,16 @@ def gbr_metrics(handles, xyz, xyz_t=None):
 def gbr_metrics_nonfp(handles, xyz):
     n = len(handles)
     _check(lib().gbr_metrics_nonfp(_arr(handles), n, _arr(xyz)), handles[0] if n else None)
+
+
+def gbr_set_sponge(h, sigma, ref=None):
+    """sigma: device pointer (int) to ncell doubles, or None to remove the
+    sponge; ref: reference primitive state (rho, u, v, w, p)."""
+    if sigma is None:
+        _check(lib().gbr_set_sponge(h, None, None), h)
+        return
+    r = (C.c_double * 5)(*[float(v) for v in ref])
+    _check(lib().gbr_set_sponge(h, C.c_void_p(sigma), r), h)
 
 
 def gbr_rhs(handles, Q, res):
@@ -326,7 +345,8 @@ class Grid:
         self.ndim = int(grid["ndim"])
         self.nvar = self.ndim + 2
         self.moving = grid.get("xyz_t") is not None or params.pop("moving", False)
-        self.cfg = make_config(self.n, self.ndim, grid["off"], moving=self.moving, **params)
+        self.bc = grid.get("bc")
+        self.cfg = make_config(self.n, self.ndim, grid["off"], moving=self.moving, bc=self.bc, **params)
         self.precision = self.cfg.precision
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.h = gbr_grid_create(self.cfg)
@@ -351,6 +371,10 @@ class Grid:
 
     def metrics_nonfp(self, xyz):
         gbr_metrics_nonfp([self.h], [xyz])
+
+    def set_sponge(self, sigma, ref=None):
+        """sigma: device tensor of ncell doubles (copied), or None."""
+        gbr_set_sponge(self.h, _ptr(sigma) if sigma is not None else None, ref)
 
     def rhs(self, Q, res):
         gbr_rhs([self.h], [Q], [res])

@@ -48,6 +48,21 @@ def test_grid_bytes_and_validation():
         assert gbr.gbr_grid_bytes(gbr.make_config(**kw)) == 0, b
 
 
+def test_boundary_config_validation():
+    """Boundary types: both sides of a direction periodic or neither, at
+    least 2 GBR_NG + 12 cells along a bounded direction, only d < ndim."""
+    off = [[1, 0, 0], [0, 1, 0], [0, 0, 1]]
+    ok = gbr.make_config((24, 30, 8), 3, off, bc=[("inflow", "outflow"), ("wall", "wall")])
+    assert gbr.gbr_grid_bytes(ok) > 0
+    for bc, n, nd in [([("inflow", "periodic")], (24, 30, 8), 3),
+                      ([("periodic", "wall")], (24, 30, 8), 3),
+                      ([("inflow", "outflow")], (23, 30, 8), 3),
+                      ([("periodic", "periodic"), ("periodic", "periodic"), ("wall", "wall")], (24, 24, 1), 2),
+                      ([(7, 0)], (24, 30, 8), 3)]:
+        assert gbr.gbr_grid_bytes(gbr.make_config(n, nd, off, bc=bc)) == 0, bc
+    assert gbr.lib().gbr_set_sponge(None, None, None) == gbr.GBR_E_ARG
+
+
 def test_null_arguments_rejected_without_device_work():
     L = gbr.lib()
     assert L.gbr_grid_create(None, None, None) == gbr.GBR_E_ARG

@@ -1,0 +1,260 @@
+"""Non-periodic boundaries on the GPU (ghost cells of Sec. 6, App. C
+metrics, sponge) against the FP64 oracle, through the C ABI.
+
+Bar: metrics within 1e-12 of the oracle per slot family (ghost slots
+included); RHS and steps within 1e-12 max relative error per variable
+(ghost residuals exactly zero, ghost states of a step as the oracle sets
+them); FP32-bulk RHS within 2e-4 (the single-grid FP32-bulk bound).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+NG = W.NG
+
+
+@pytest.fixture(scope="module")
+def gbr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2303_10785_amd import gbr as G
+    G.lib()
+    return G
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(gpu, ref):
+    worst = 0.0
+    for v in range(ref.shape[0]):
+        s = float(np.abs(ref[v]).max())
+        d = float(np.abs(gpu[v] - ref[v]).max())
+        worst = max(worst, d / s if s > 0 else d)
+    return worst
+
+
+def families(G):
+    fam = {
+        "cell_hat": [(oracle.M_HAT(d, c), G.SLOT_CELL_HAT(d, c)) for d in range(3) for c in range(3)],
+        "cell_unhat": [(oracle.M_UNHAT(d, c), G.SLOT_CELL_UNHAT(d, c)) for d in range(3) for c in range(3)],
+        "j": [(oracle.M_J, G.SLOT_CELL_J)],
+        "invj": [(oracle.M_INVJ, G.SLOT_CELL_INVJ)],
+        "invjt": [(oracle.M_INVJT, G.SLOT_CELL_INVJT)],
+    }
+    for f in range(3):
+        fam[f"face{f}_hat"] = [(oracle.M_FHAT(f, c), G.SLOT_FACE_HAT(f, c)) for c in range(3)]
+        fam[f"face{f}_unhat"] = [(oracle.M_FUNHAT(f, e, c), G.SLOT_FACE_UNHAT(f, e, c))
+                                 for e in range(3) for c in range(3)]
+    return fam
+
+
+GRIDS = {
+    "wavy2d_inout": lambda: W.bounded(W.wavy2d((40, 20), amp=0.1, rand=0.1, seed=2), [("inflow", "outflow")]),
+    "wavy2d_walls": lambda: W.bounded(W.wavy2d((36, 30), amp=0.1), [("inflow", "outflow"), ("wall", "wall")]),
+    "random3d_inout": lambda: W.bounded(W.random3d((26, 9, 7), seed=3), [("inflow", "outflow")]),
+    "sinusoidal3d_yz": lambda: W.bounded(W.sinusoidal3d((10, 25, 26)),
+                                         [("periodic", "periodic"), ("outflow", "outflow"), ("wall", "outflow")]),
+    "jet3d_all": lambda: W.bounded(W.jet3d((70, 26, 25)), [("inflow", "outflow"), ("outflow", "outflow"),
+                                                          ("outflow", "outflow")]),
+}
+
+
+def grid_and_metrics(gbr, g, **params):
+    h = gbr.Grid(g, **params)
+    h.metrics(dev(g["xyz"]))
+    return h
+
+
+@pytest.mark.parametrize("name", sorted(GRIDS))
+def test_bounded_metrics(gbr, name):
+    g = GRIDS[name]()
+    h = grid_and_metrics(gbr, g)
+    torch.cuda.synchronize()
+    m = oracle.metrics(g)
+    worst = {}
+    for fam, pairs in families(gbr).items():
+        if g["ndim"] == 2 and fam.startswith("face2"):
+            continue
+        ref = np.stack([m[o] for o, _ in pairs])
+        got = np.stack([h.metric(s).cpu().numpy() for _, s in pairs])
+        scale = float(np.abs(ref).max())
+        worst[fam] = float(np.abs(got - ref).max()) / scale if scale > 1e-300 else float(np.abs(got - ref).max())
+    say(f"[bounded metrics] {name}: worst {max(worst.values()):.3e} ({max(worst, key=worst.get)})")
+    h.close()
+    assert max(worst.values()) <= TOL, worst
+
+
+def jet_sponge(g):
+    sig = W.sponge_sigma(g, width=8, amp=1.5, power=2.0,
+                         sides=[(0, 1), (1, 0), (1, 1), (2, 0), (2, 1)])
+    return sig, (1.0, 0.0, 0.0, 0.0, 1.0 / 1.4)
+
+
+RHS_CASES = [
+    ("euler_mp_inout_2d", "wavy2d_inout", dict(viscous=False, limiter="mp"),
+     lambda g: W.random_smooth_state(g, seed=4), None),
+    ("ns_ducros_walls_2d", "wavy2d_walls", dict(viscous=True, limiter="ducros", theta_c=0.3, Re=300.0),
+     lambda g: W.random_rough_state(g, seed=5, amp=0.2), None),
+    ("euler_none_walls_2d", "wavy2d_walls", dict(viscous=False, limiter="none"),
+     lambda g: W.shu_vortex(g, eps=2.0), None),
+    ("ns_mp_inout_3d", "random3d_inout", dict(viscous=True, limiter="mp", Re=500.0),
+     lambda g: W.random_smooth_state(g, seed=6), None),
+    ("euler_mp_yz_3d", "sinusoidal3d_yz", dict(viscous=False, limiter="mp"),
+     lambda g: W.random_smooth_state(g, seed=7), None),
+    ("ns_ducros_jet", "jet3d_all", dict(viscous=True, limiter="ducros", Re=1.144e6),
+     lambda g: W.jet_ic(g), None),
+    ("ns_ducros_jet_sponge", "jet3d_all", dict(viscous=True, limiter="ducros", Re=1.144e6),
+     lambda g: W.jet_ic(g), jet_sponge),
+]
+
+
+@pytest.mark.parametrize("case", RHS_CASES, ids=[c[0] for c in RHS_CASES])
+def test_bounded_rhs(gbr, case):
+    name, gname, params, state, sponge = case
+    g = GRIDS[gname]()
+    Q = state(g)
+    extra = {}
+    h = grid_and_metrics(gbr, g, **params)
+    if sponge is not None:
+        sig, ref = sponge(g)
+        h.set_sponge(dev(sig), ref)
+        extra = dict(sigma=sig, qref=ref)
+    Qd = dev(Q)
+    res = torch.full_like(Qd, 5.0)
+    h.rhs(Qd, res)
+    torch.cuda.synchronize()
+    assert h.check_state() == gbr.GBR_OK
+    assert torch.equal(Qd.cpu(), torch.from_numpy(Q))  # the state is not written
+    ref = oracle.rhs(g, oracle.metrics(g), Q, **params, **extra)
+    got = res.cpu().numpy()
+    e = rel(got, ref)
+    mask = np.ones(Q.shape[1:], bool)
+    mask[oracle.interior(g)] = False
+    say(f"[bounded rhs] {name}: max rel err {e:.3e}")
+    h.close()
+    assert np.all(got[:, mask] == 0.0)
+    assert e <= TOL
+
+
+STEP_CASES = [
+    ("euler_mp_2d_walls", "wavy2d_walls", dict(viscous=False, limiter="mp"),
+     lambda g: W.shu_vortex(g, eps=2.0), None, 4),
+    ("ns_ducros_3d_inout", "random3d_inout", dict(viscous=True, limiter="ducros", theta_c=0.3, Re=500.0),
+     lambda g: W.random_smooth_state(g, seed=12), None, 2),
+    ("ns_ducros_jet_sponge", "jet3d_all", dict(viscous=True, limiter="ducros", Re=1.144e6),
+     lambda g: W.jet_ic(g), jet_sponge, 3),
+]
+
+
+@pytest.mark.parametrize("case", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_bounded_steps(gbr, case):
+    name, gname, params, state, sponge, nsteps = case
+    g = GRIDS[gname]()
+    Q = state(g)
+    extra = {}
+    h = grid_and_metrics(gbr, g, **params)
+    if sponge is not None:
+        sig, ref = sponge(g)
+        h.set_sponge(dev(sig), ref)
+        extra = dict(sigma=sig, qref=ref)
+    m = oracle.metrics(g)
+    Qd = dev(Q)
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for s in range(nsteps):
+        h.step(Qd, 0.4, gbr.GBR_DT_CFL, dt_out=dt)
+        Q, dt_ref = oracle.step(g, m, Q, 0.4, **params, **extra)
+        torch.cuda.synchronize()
+        e = rel(Qd.cpu().numpy(), Q)
+        say(f"[bounded step] {name} step {s}: max rel err {e:.3e}, dt {dt.item():.6e} (oracle {dt_ref:.6e})")
+        assert e <= TOL and abs(dt.item() - dt_ref) <= TOL * dt_ref
+    assert h.check_state() == gbr.GBR_OK
+    h.close()
+
+
+def test_bounded_fp32_bulk_rhs(gbr):
+    g = GRIDS["random3d_inout"]()
+    params = dict(viscous=True, limiter="mp", Re=500.0)
+    Q = W.random_smooth_state(g, seed=13)
+    h = grid_and_metrics(gbr, g, precision="fp32_bulk", **params)
+    res = torch.empty(Q.shape, dtype=torch.float32, device="cuda")
+    h.rhs(dev(Q), res)
+    torch.cuda.synchronize()
+    ref = oracle.rhs(g, oracle.metrics(g), Q, **params)
+    e = rel(res.double().cpu().numpy(), ref)
+    say(f"[bounded fp32 rhs] {e:.3e}")
+    h.close()
+    assert e <= 2e-4
+
+
+def test_bounded_cfl_and_rk_ignore_ghosts(gbr):
+    g = GRIDS["sinusoidal3d_yz"]()
+    params = dict(viscous=True, limiter="mp", Re=200.0)
+    Q = W.random_smooth_state(g, seed=2)
+    mask = np.ones(Q.shape[1:], bool)
+    mask[oracle.interior(g)] = False
+    Qg = Q.copy()
+    Qg[1][mask] *= 40.0
+    h = grid_and_metrics(gbr, g, **params)
+    dts = []
+    for q in (Q, Qg):
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        gbr.gbr_cfl([h.h], [dev(q)], 0.5, [dt])
+        torch.cuda.synchronize()
+        dts.append(dt.item())
+    assert dts[0] == dts[1]
+    assert abs(dts[0] - 0.5 * oracle.cfl_min(g, oracle.metrics(g), Q, **params)) <= TOL * dts[0]
+    Qd = dev(Qg)
+    res = torch.ones_like(Qd)
+    dt = torch.full((1,), 0.1, dtype=torch.float64, device="cuda")
+    gbr.gbr_rk_stage([h.h], 0, [dt], [dev(Q)], [Qd], [res])
+    torch.cuda.synchronize()
+    out = Qd.cpu().numpy()
+    assert np.array_equal(out[:, mask], Qg[:, mask])
+    want = oracle.rk_stage(g, oracle.metrics(g), 0, 0.1, Q, Qg, np.ones_like(Q), **params)
+    assert rel(out, want) <= TOL
+    h.close()
+
+
+def test_bounded_rejections(gbr):
+    g = GRIDS["random3d_inout"]()
+    with pytest.raises(gbr.GbrError) as ei:
+        gbr.Grid(g, scheme="mig4")
+    assert ei.value.status == gbr.GBR_E_UNSUPPORTED
+    mv = W.bounded(W.Deforming3D((26, 8, 8), seed=1).at(0.1), [("inflow", "outflow")])
+    with pytest.raises(gbr.GbrError) as ei:
+        gbr.Grid(mv)
+    assert ei.value.status == gbr.GBR_E_UNSUPPORTED
+    bad = dict(W.wavy2d((40, 20)), bc=[("inflow", "periodic")])
+    with pytest.raises(gbr.GbrError) as ei:
+        gbr.Grid(bad)
+    assert ei.value.status == gbr.GBR_E_ARG
+    short = dict(W.wavy2d((20, 20)), bc=[("inflow", "outflow")])
+    with pytest.raises(gbr.GbrError) as ei:
+        gbr.Grid(short)
+    assert ei.value.status == gbr.GBR_E_ARG
+    h = grid_and_metrics(gbr, g)
+    Q = dev(W.random_smooth_state(g, seed=1))
+    for call in (lambda: h.metrics_nonfp(dev(g["xyz"])),
+                 lambda: h.diagnostics(Q)):
+        with pytest.raises(gbr.GbrError) as ei:
+            call()
+        assert ei.value.status == gbr.GBR_E_UNSUPPORTED
+    h.close()
+    g2 = GRIDS["wavy2d_inout"]()
+    h2 = grid_and_metrics(gbr, g2, viscous=False, limiter="mp")
+    with pytest.raises(gbr.GbrError) as ei:
+        gbr.Batch([h2], [dev(W.random_smooth_state(g2, seed=2))])
+    assert ei.value.status == gbr.GBR_E_UNSUPPORTED
+    h2.close()
