@@ -442,15 +442,17 @@ __global__ void __launch_bounds__(kBlock) k_bc_state(Dims dm, Slab s, BcTypes bt
     for (int v = 0; v < NV; ++v) Q[v * N + gc] = q[v];
 }
 
+// Ghost sensor values of the slab of one bounded direction: the value of
+// the nearest interior cell (clamped along every bounded direction, so a
+// corner ghost visited by two slabs gets the same value from both).
 template <class R>
-__global__ void __launch_bounds__(kBlock) k_theta_ghosts(Dims dm, R *theta)
+__global__ void __launch_bounds__(kBlock) k_theta_ghosts(Dims dm, Slab s, R *theta)
 {
-    const long idx = blockIdx.x * (long)kBlock + threadIdx.x;
-    if (idx >= dm.ncell) return;
-    int ijk[3];
-    unpack(dm, idx, ijk);
-    const long cc = clamp_to(dm, ijk, -1);
-    if (cc != idx) theta[idx] = theta[cc];
+    const long e = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (e >= s.count) return;
+    int t[3], side, depth;
+    slab_cell(dm, s, e, t, &side, &depth);
+    theta[pack(dm, t)] = theta[clamp_to(dm, t, -1)];
 }
 
 struct QRef {
@@ -546,9 +548,13 @@ template <class R>
 hipError_t launch_theta_ghosts(gbr_grid_s *g, R *theta)
 {
     const Dims dm = dims_of(g);
-    const unsigned blocks = unsigned((dm.ncell + kBlock - 1) / kBlock);
     Timed timed(g, GBR_K_CELL_GRAD);
-    hipLaunchKernelGGL((k_theta_ghosts<R>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, theta);
+    for (int d = 0; d < g->cfg.ndim; ++d) {
+        if (g->cfg.bc[d][0] == GBR_BC_PERIODIC) continue;
+        const Slab s = slab_of(dm, d);
+        const unsigned blocks = unsigned((s.count + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL((k_theta_ghosts<R>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, s, theta);
+    }
     return hipGetLastError();
 }
 

@@ -246,7 +246,13 @@ __global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
 // the xi and eta derivatives; the zeta derivative comes from a 7-deep register
 // window along the thread's own column, so every value is read from HBM about
 // once.
-constexpr int GI = 32, GJ = kBlock / GI, KC = 16, HI = GI + 6, HJ = GJ + 6;
+#ifndef GBR_GRAD_GI
+#define GBR_GRAD_GI 32
+#endif
+#ifndef GBR_GRAD_KC
+#define GBR_GRAD_KC 16
+#endif
+constexpr int GI = GBR_GRAD_GI, GJ = kBlock / GI, KC = GBR_GRAD_KC, HI = GI + 6, HJ = GJ + 6;
 
 template <int NDIM, bool SENSOR, class R>
 __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)

@@ -351,3 +351,32 @@ def test_step_keeps_inflow_ghosts_and_refills_others():
     assert np.array_equal(Q1[:, NG:-NG, :NG], Q[:, NG:-NG, :NG])
     assert np.array_equal(Q1, oracle.apply_bc(g, m, Q1, **params))
     assert np.abs(Q1 - Q).max() > 1e-6
+
+
+@pytest.mark.parametrize("params", [dict(viscous=False, limiter="mp"),
+                                    dict(viscous=True, limiter="ducros", theta_c=0.2, Re=200.0)],
+                         ids=["euler_mp", "ns_ducros"])
+def test_wall_box_conserves_mass_energy_and_tangential_momentum(params):
+    """Slip walls (mirror ghosts) on a Cartesian box, periodic along x: the
+    HLLC contact speed of mirrored states is zero, and the viscous shear and
+    heat flux of a mirrored flow vanish at the wall, so the interior sums of
+    rho/J, E/J and the wall-tangential momentum stay constant over steps."""
+    nx, ny = 16, 12 + 2 * NG
+    g = W.bounded(_cartesian2d(nx, ny, 0.3, 0.25, y0=-NG * 0.25), [("periodic", "periodic"), ("wall", "wall")])
+    x, y = g["xyz"][0], g["xyz"][1]
+    Lx = nx * 0.3
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x / Lx) * np.cos(1.3 * y)
+    u = 0.3 + 0.1 * np.cos(2 * np.pi * x / Lx)
+    v = 0.2 * np.sin(2.1 * y) * np.cos(2 * np.pi * x / Lx)
+    p = 1.0 / 1.4 + 0.05 * np.sin(2 * np.pi * x / Lx + 0.4)
+    Q = W.conserved(rho, u, v, 0 * u, p, ndim=2)
+    m = oracle.metrics(g)
+    inner = (slice(None),) + oracle.interior(g)
+    vol = m[oracle.M_INVJ][oracle.interior(g)]
+    tot0 = [(Q[inner][q] * vol).sum() for q in range(4)]
+    for _ in range(4):
+        Q, _ = oracle.step(g, m, Q, 0.4, **params)
+    tot = [(Q[inner][q] * vol).sum() for q in range(4)]
+    for q in (0, 1, 3):  # mass, x-momentum (tangential to the walls), energy
+        assert abs(tot[q] - tot0[q]) <= 1e-13 * abs(tot0[q]), (q, tot[q] - tot0[q])
+    assert abs(tot[2] - tot0[2]) > 1e-8  # the walls push on the normal momentum
