@@ -238,9 +238,12 @@ gbr_status gbr_diagnostics(const gbr_grid *g, int n, const double *const *Q, dou
 
 /* Sponge layers (Sec. 8.3, after Bodony): the right-hand side gains the
  * relaxation source -sigma (Q - Q_ref), i.e. Res += -sigma (Q - Q_ref) / J,
- * in interior cells. sigma: device pointer to ncell doubles (>= 0; zero
- * outside the layers), copied into library memory on g's stream before the
- * call returns (the caller may free it afterwards). ref: host pointer to
+ * in interior cells (every cell of a periodic grid). sigma: device pointer
+ * to ncell doubles (>= 0; zero outside the layers), copied into library
+ * memory (ncell doubles, allocated on the first call and kept until
+ * gbr_grid_destroy or a call with sigma == NULL; not counted by
+ * gbr_grid_bytes) on g's stream before the call returns (the caller may
+ * free it afterwards). ref: host pointer to
  * the reference primitive state (rho, u, v, w, p); w is ignored in 2-D.
  * sigma == NULL removes the sponge. Errors: GBR_E_ARG (null g, null ref
  * with non-null sigma, rho or p <= 0), GBR_E_NOMEM, GBR_E_DEVICE.          */

@@ -41,6 +41,9 @@ constexpr int kBlock = 256;
 #ifndef GBR_TS_CROSS
 #define GBR_TS_CROSS 16
 #endif
+#ifndef GBR_COMPACT_DIRS
+#define GBR_COMPACT_DIRS 7  // bit D: gather the sensor-flagged interfaces of sweep D (FP64)
+#endif
 
 template <class R>
 struct PhysR {
@@ -433,7 +436,7 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     bool limited = ph.limiter == GBR_LIM_MP;
     // (FP64 only: in FP32 the scattered LDS reads cost more than the
     // divergence they remove)
-    constexpr bool compact = sizeof(R) == 8;
+    constexpr bool compact = sizeof(R) == 8 && ((GBR_COMPACT_DIRS >> D) & 1);
     if (compact && ph.limiter == GBR_LIM_DUCROS) {
         __shared__ int s_order[kBlock];
         __shared__ int s_count[kBlock / 64];

@@ -283,3 +283,30 @@ def test_wall_box_conservation_on_gpu(gbr):
     h.close()
     assert abs(tot[0] - tot0[0]) <= 1e-12 * abs(tot0[0])
     assert abs(tot[3] - tot0[3]) <= 1e-12 * abs(tot0[3])
+
+
+def test_sponge_on_periodic_grid_and_removal(gbr):
+    """The sponge also applies on a periodic grid (every cell interior); a
+    call with sigma = NULL removes it."""
+    g = W.random3d((12, 10, 9), seed=4)
+    params = dict(viscous=True, limiter="ducros", theta_c=0.3, Re=400.0)
+    Q = W.random_smooth_state(g, seed=5)
+    sig = np.random.default_rng(7).uniform(0.0, 3.0, Q.shape[1:])
+    ref = (1.1, 0.2, -0.1, 0.05, 0.8)
+    h = grid_and_metrics(gbr, g, **params)
+    h.set_sponge(dev(sig), ref)
+    m = oracle.metrics(g)
+    res = torch.empty_like(dev(Q))
+    h.rhs(dev(Q), res)
+    want = oracle.rhs(g, m, Q, sigma=sig, qref=ref, **params)
+    e = rel(res.cpu().numpy(), want)
+    Qd = dev(Q)
+    h.step(Qd, 0.3, gbr.GBR_DT_CFL)
+    Qs, _ = oracle.step(g, m, Q, 0.3, sigma=sig, qref=ref, **params)
+    es = rel(Qd.cpu().numpy(), Qs)
+    h.set_sponge(None)
+    h.rhs(dev(Q), res)
+    e0 = rel(res.cpu().numpy(), oracle.rhs(g, m, Q, **params))
+    say(f"[sponge periodic] rhs {e:.3e}, step {es:.3e}, after removal {e0:.3e}")
+    h.close()
+    assert e <= TOL and es <= TOL and e0 <= TOL
