@@ -325,6 +325,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-grid leg")
+    ap.add_argument("--no-bounded", action="store_true",
+                    help="skip the bounded spatial-jet leg (it launches the same kernels at another size, "
+                         "so profiles of the periodic workload leave it out)")
     args = ap.parse_args()
     if args.gpus != 1:
         log(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -414,7 +417,7 @@ def main():
     # against the FP64 path (which matches the oracle to 1e-12)
     fp32 = fp32_bulk_leg(G, grid, Q0, args, dev, ncell)
     mig4 = mig4_leg(grid, Q0, args, dev, ncell)
-    bounded = bounded_leg(args, dev)
+    bounded = None if args.no_bounded else bounded_leg(args, dev)
 
     line = {
         "metric": "cell-updates/s per RHS at 13M cells (% HBM peak); batched solves/s + p99 latency",
