@@ -247,19 +247,30 @@ __global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
 // Gradient tile: GI x GJ cells in the (i, j) plane, marching KC planes along
 // k. Each k plane of (u, v, w, T) is staged in LDS with a 3-cell i/j halo for
 // the xi and eta derivatives; the zeta derivative comes from a 7-deep register
-// window along the thread's own column, so every value is read from HBM about
-// once.
-#ifndef GBR_GRAD_GI
-#define GBR_GRAD_GI 32
+// window along the thread's own column, which also supplies the tile's own
+// cells of the LDS plane, so only the halo is read a second time.
+// 16 x 16 tiles in FP64, where the smaller halo pays; 32 x 8 in FP32-bulk,
+// where the wider rows do (both measured on the 13 M jet workload).
+#ifndef GBR_GRAD_GI64
+#define GBR_GRAD_GI64 16
+#endif
+#ifndef GBR_GRAD_GI32
+#define GBR_GRAD_GI32 32
 #endif
 #ifndef GBR_GRAD_KC
 #define GBR_GRAD_KC 16
 #endif
-constexpr int GI = GBR_GRAD_GI, GJ = kBlock / GI, KC = GBR_GRAD_KC, HI = GI + 6, HJ = GJ + 6;
+template <class R>
+struct GradTile {
+    static constexpr int GI = sizeof(R) == 8 ? GBR_GRAD_GI64 : GBR_GRAD_GI32;
+    static constexpr int GJ = kBlock / GI, KC = GBR_GRAD_KC, HI = GI + 6, HJ = GJ + 6;
+};
 
 template <int NDIM, bool SENSOR, class R>
 __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
 {
+    constexpr int GI = GradTile<R>::GI, GJ = GradTile<R>::GJ, KC = GradTile<R>::KC;
+    constexpr int HI = GradTile<R>::HI, HJ = GradTile<R>::HJ;
     __shared__ R sp[4][HJ][HI];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
@@ -287,10 +298,19 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
             const long c = pack(dm, ic, jc, wrap_index(k + 3, nk));
 #pragma unroll
             for (int s = 0; s < 4; ++s) win[6][s] = f[s][c];
+            // the tile's own cells of plane k are already in the register
+            // window (read three planes ago, long evicted from L2 by the
+            // other resident tiles): only the halo comes from memory
+            if (inside) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) sp[s][tj + 3][ti + 3] = win[3][s];
+            }
         }
         for (int e = threadIdx.x; e < HI * HJ; e += kBlock) {
             const int x = e % HI, y = e / HI;
-            const long c = pack(dm, wrap_index(i0 - 3 + x, ni), wrap_index(j0 - 3 + y, nj), k);
+            const int gi = i0 - 3 + x, gj = j0 - 3 + y;
+            if (NDIM == 3 && x >= 3 && x < GI + 3 && y >= 3 && y < GJ + 3 && gi < ni && gj < nj) continue;
+            const long c = pack(dm, wrap_index(gi, ni), wrap_index(gj, nj), k);
 #pragma unroll
             for (int s = 0; s < 4; ++s) sp[s][y][x] = f[s][c];
         }
@@ -880,8 +900,9 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
     // cell gradients feed only the tangential viscous terms and the sensor
     if (VISC || a.pr.limiter == GBR_LIM_DUCROS) {
         Timed timed(g, GBR_K_CELL_GRAD);
-        dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
-                unsigned((a.dm.n[2] + KC - 1) / KC));
+        using GT = GradTile<R>;
+        dim3 gg(unsigned(((a.dm.n[0] + GT::GI - 1) / GT::GI) * ((a.dm.n[1] + GT::GJ - 1) / GT::GJ)),
+                unsigned((a.dm.n[2] + GT::KC - 1) / GT::KC));
         if (a.pr.limiter == GBR_LIM_DUCROS)
             hipLaunchKernelGGL((k_cell_grad<NDIM, true, R>), gg, dim3(kBlock), 0, g->stream, a);
         else
@@ -960,8 +981,9 @@ hipError_t diag_typed(gbr_grid_s *g, const double *Q, double *fields, double *in
             ig4_grad<1, 2, R>(g, a, st);
         }
     } else {
-        dim3 gg(unsigned(((a.dm.n[0] + GI - 1) / GI) * ((a.dm.n[1] + GJ - 1) / GJ)),
-                unsigned((a.dm.n[2] + KC - 1) / KC));
+        using GT = GradTile<R>;
+        dim3 gg(unsigned(((a.dm.n[0] + GT::GI - 1) / GT::GI) * ((a.dm.n[1] + GT::GJ - 1) / GT::GJ)),
+                unsigned((a.dm.n[2] + GT::KC - 1) / GT::KC));
         if (nd == 3)
             hipLaunchKernelGGL((k_cell_grad<3, false, R>), gg, dim3(kBlock), 0, g->stream, a);
         else
