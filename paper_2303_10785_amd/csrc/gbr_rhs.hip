@@ -73,6 +73,7 @@ struct RhsArgs {
     R *prim_out;       // primitives of the updated state for the next stage, or null
     const double *sigma;  // sponge strength per cell (fused stage), or null
     double qref[5];       // sponge reference state, conserved
+    int moving;           // grid velocities present (temporal metrics non-zero)
 };
 
 __device__ __forceinline__ long pack(const Dims &dm, int i, int j, int k)
@@ -367,11 +368,14 @@ struct Tile {
 };
 
 
-#ifdef GBR_SWEEP_MINWAVES
-#define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock, GBR_SWEEP_MINWAVES)
-#else
-#define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock)
+// At least three 256-thread workgroups per CU (3 waves per SIMD, at most 168
+// VGPRs): the FP64 sweeps sit at 160-168 registers, and one more register
+// (the MIG4 sweep with the fused RK stage reached 170) would cost a third of
+// the occupancy; the bound trades that for a 4-register spill there.
+#ifndef GBR_SWEEP_MINWAVES
+#define GBR_SWEEP_MINWAVES 3
 #endif
+#define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock, GBR_SWEEP_MINWAVES)
 // MODE: 0 writes Res, 1 adds to Res, 2 adds to Res and applies the SSP-RK3
 // stage to the tile's own cells (the last sweep of a gbr_step stage).
 template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R>
@@ -495,6 +499,8 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     R PL[5], PR[5];
     if (limited) {
+        // the normal is read here and again for the flux: keeping it live
+        // across the limiter costs a wave of occupancy in FP64
         R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
         R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
         R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
@@ -508,8 +514,9 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     }
     bool ok = PL[0] > R(0) && PL[4] > R(0) && PR[0] > R(0) && PR[4] > R(0);
 
-    // HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2)
-    const R nt = R(m[GBR_SLOT_FACE_HATT(D) * N + ca]);
+    // HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2); the
+    // temporal metric is zero on static grids and not read there
+    const R nt = a.moving ? R(m[GBR_SLOT_FACE_HATT(D) * N + ca]) : R(0);
     const R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
     const R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
     const R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
@@ -944,6 +951,7 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.prim_out = nullptr;
     a.sigma = g->sigma;
     for (int v = 0; v < 5; ++v) a.qref[v] = g->qref[v];
+    a.moving = g->cfg.moving;
     return a;
 }
 
