@@ -41,6 +41,9 @@ constexpr int kBlock = 256;
 #ifndef GBR_TS_CROSS
 #define GBR_TS_CROSS 16
 #endif
+#ifndef GBR_TS_XI
+#define GBR_TS_XI 64
+#endif
 #ifndef GBR_COMPACT_DIRS
 #define GBR_COMPACT_DIRS 7  // bit D: gather the sensor-flagged interfaces of sweep D (FP64)
 #endif
@@ -350,7 +353,7 @@ template <int D>
 struct Tile {
     // faces per tile along D, lanes across, and index roles:
     // s = sweep direction D, c = cross direction, o = outer direction.
-    static constexpr int TS = (D == 0) ? 64 : GBR_TS_CROSS;
+    static constexpr int TS = (D == 0) ? GBR_TS_XI : GBR_TS_CROSS;
     static constexpr int TC = kBlock / TS;
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
