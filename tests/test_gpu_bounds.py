@@ -341,3 +341,27 @@ def test_bounded_jet_long_run(gbr):
     say(f"[bounded jet long run] 300 steps: interior x-momentum {mom:.4e}, max rho {Qn[0].max():.3f}")
     h.close()
     assert mom > 0.0
+
+
+def test_bounded_fp32_bulk_steps(gbr):
+    """FP32-bulk steps on a bounded grid with walls, inflow, outflow and a
+    sponge, against the FP64 oracle (the single-grid FP32-bulk step bound,
+    1e-5 per step, on smooth data)."""
+    g = GRIDS["wavy2d_walls"]()
+    params = dict(viscous=False, limiter="mp")
+    Q = W.shu_vortex(g, eps=2.0)
+    sig = W.sponge_sigma(g, width=6, amp=1.0, power=2.0, sides=[(0, 1)])
+    ref = (1.0, 1.0, 1.0, 0.0, 1.0)
+    h = grid_and_metrics(gbr, g, precision="fp32_bulk", **params)
+    h.set_sponge(dev(sig), ref)
+    m = oracle.metrics(g)
+    Qd = dev(Q)
+    for s in range(3):
+        h.step(Qd, 0.4, gbr.GBR_DT_CFL)
+        Q, _ = oracle.step(g, m, Q, 0.4, sigma=sig, qref=ref, **params)
+        torch.cuda.synchronize()
+        e = rel(Qd.cpu().numpy(), Q)
+        say(f"[bounded fp32 step] step {s}: max rel err vs FP64 oracle {e:.3e}")
+        assert e <= 1e-5
+    assert h.check_state() == gbr.GBR_OK
+    h.close()
