@@ -40,12 +40,14 @@ PAPER_CONTEXT = {
 ALG_BYTES_PER_CELL = {
     "prims": 40 + 48,                     # Q -> rho, u, v, w, p, T
     "cell_grad": 32 + 72 + 96 + 8,        # u, v, w, T, 9 cell metrics -> 12 gradients, theta
-    "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40,   # 5 primitives + T, 12 face metrics, 8 tangential
-                                             # grads, T', theta -> Res out
-    "sweep_eta": 48 + 96 + 64 + 8 + 8 + 80,  # ... Res in and out
-    # last sweep with the SSP-RK3 stage fused: Res in; Q, Qn, J, (1/J)_t in;
-    # Q out; the next stage's primitives out in two of the three stages
-    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 40 + 96 + 40 + (2 * 48) / 3,
+    # the sweeps run zeta, eta, xi: zeta writes Res, eta adds to it, and xi,
+    # last, applies the SSP-RK3 stage
+    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 40,  # 5 primitives + T, 12 face metrics, 8 tangential
+                                              # grads, T', theta -> Res out
+    "sweep_eta": 48 + 96 + 64 + 8 + 8 + 80,   # ... Res in and out
+    # with the stage fused: Res in; Q, Qn, J, (1/J)_t in; Q out; the next
+    # stage's primitives out in two of the three stages
+    "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40 + 96 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     "cfl": 40 + 72 + 24,                  # Q, 9 cell metrics, 3 temporal metrics
 }

@@ -174,7 +174,8 @@ gbr_status gbr_metrics_nonfp(const gbr_grid *g, int n, const double *const *xyz)
 
 /* Right-hand side Res = d(Q/J)/dt (Sec. 3, Sec. 5.1 Steps 1-7, Sec. 5.2
  * Steps 1-5): res[b] receives -sum_d [Phi(+1/2) - Phi(-1/2)] with
- * Phi = F - F^v, the directions accumulated in the order xi, eta, zeta.
+ * Phi = F - F^v, the directions accumulated in the order zeta, eta, xi
+ * (eta, xi in 2-D).
  * Q[b]: conserved state (read only, double). res[b]: output, nvar arrays of
  * double (GBR_FP64) or float (GBR_FP32_BULK); must not alias Q[b].
  * Bounded grids: ghost primitives come from the boundary types (Q itself

@@ -16,8 +16,10 @@
 //                   the characteristic (limited) or direct van Leer states,
 //                   HLLC and the alpha-damping viscous flux. The fluxes go
 //                   back to LDS and each cell accumulates
-//                   -(Phi(+1/2) - Phi(-1/2)) into Res (written by the xi
-//                   sweep, updated by the others).
+//                   -(Phi(+1/2) - Phi(-1/2)) into Res (written by the first
+//                   sweep, zeta in 3-D and eta in 2-D, updated by the others;
+//                   in gbr_step the xi sweep comes last and applies the
+//                   SSP-RK3 stage).
 // Tiles along D overlap by one interface, so no cell needs a flux computed by
 // another workgroup.
 //
@@ -744,7 +746,7 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
 }
 
 template <int D, int NDIM, bool VISC, class R, bool IG4>
-hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
+hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode)
 {
     using T = Tile<D>;
     const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
@@ -752,13 +754,27 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk = false)
     const int tiles_c = (nc + T::TC - 1) / T::TC;
     dim3 grid(unsigned(tiles_s * tiles_c), unsigned(no));
     Timed timed(g, GBR_K_SWEEP_XI + D);
-    if (D == 0)
+    if (mode == 0)
         hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
-    else if (!fuse_rk)
+    else if (mode == 1)
         hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
     else
         hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
+}
+
+// The sweeps of one RHS in the order zeta, eta, xi (eta, xi in 2-D): the
+// first writes Res, the others add to it, and with fuse_rk the xi sweep
+// applies the SSP-RK3 stage. The stage's extra traffic (Q, Qn, J, (1/J)_t
+// in, Q and the next primitives out) coalesces best in the xi tiles, whose
+// rows are 64 cells (512 bytes) long against 16 in the eta / zeta tiles.
+template <int NDIM, bool VISC, class R, bool IG4>
+hipError_t sweeps(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk)
+{
+    hipError_t e;
+    if (NDIM == 3 && (e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, IG4>(g, a, 0)) != hipSuccess) return e;
+    if ((e = sweep<1, NDIM, VISC, R, IG4>(g, a, NDIM == 3 ? 1 : 0)) != hipSuccess) return e;
+    return sweep<0, NDIM, VISC, R, IG4>(g, a, fuse_rk ? 2 : 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -902,10 +918,7 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
                 hipLaunchKernelGGL((k_sensor<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = sweep<0, NDIM, VISC, R, true>(g, a)) != hipSuccess) return e;
-        if ((e = sweep<1, NDIM, VISC, R, true>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
-        if (NDIM == 3) e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, true>(g, a, fuse_rk);
-        return e;
+        return sweeps<NDIM, VISC, R, true>(g, a, fuse_rk);
     }
     // cell gradients feed only the tangential viscous terms and the sensor
     if (VISC || a.pr.limiter == GBR_LIM_DUCROS) {
@@ -921,9 +934,7 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (g->bounded && a.pr.limiter == GBR_LIM_DUCROS && (e = launch_theta_ghosts<R>(g, a.theta)) != hipSuccess)
         return e;
-    if ((e = sweep<0, NDIM, VISC, R, false>(g, a)) != hipSuccess) return e;
-    if ((e = sweep<1, NDIM, VISC, R, false>(g, a, fuse_rk && NDIM == 2)) != hipSuccess) return e;
-    if (NDIM == 3 && (e = sweep<NDIM == 3 ? 2 : 1, NDIM, VISC, R, false>(g, a, fuse_rk)) != hipSuccess) return e;
+    if ((e = sweeps<NDIM, VISC, R, false>(g, a, fuse_rk)) != hipSuccess) return e;
     // the sponge of a plain RHS (the fused stage applies it itself)
     if (!fuse_rk && g->sigma) e = launch_sponge<R>(g, a.Q, a.res);
     return e;
