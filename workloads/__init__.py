@@ -185,6 +185,53 @@ class Deforming3D:
         return _grid(self.n, 3, xyz, self.off, xyz_t)
 
 
+class Deforming2D:
+    """Deforming 2-D grid of the double periodic shear layer (Sec. 8.2,
+    Eq. DPSL-eqn1 / DPSL-eqn2):
+
+        x(t) = xmin + dx [i + A sin(2 pi w t) sin(n pi j dy / L)]
+        y(t) = ymin + dy [j + A sin(2 pi w t) sin(n pi i dx / L)]
+
+    with i, j the node indices from 0. The printed phase terms i phi / (IL - 1)
+    are taken as zero (any other value breaks the periodicity of the grid);
+    A and n, which the paper takes from its reference, default to the values
+    of its 3-D deforming case (1.5 cells, 4). Cell centres are
+    ``base + sin(2 pi w t) * mode``, velocities ``2 pi w cos(2 pi w t) * mode``.
+    """
+
+    def __init__(self, n, L=1.0, A=1.5, nmode=4, omega=1.0):
+        ni, nj = n
+        self.n, self.L, self.A, self.nmode, self.omega = (ni, nj, 1), L, A, nmode, omega
+        dx, dy = L / ni, L / nj
+        J, I = np.meshgrid(np.arange(nj + 1), np.arange(ni + 1), indexing="ij")
+        X0, Y0 = dx * I, dy * J
+        MX = dx * A * np.sin(nmode * np.pi * J * dy / L)
+        MY = dy * A * np.sin(nmode * np.pi * I * dx / L)
+        self.base = _centroids2(X0, Y0)
+        self.mode = _centroids2(MX, MY)
+        self.off = [[L, 0, 0], [0, L, 0], [0, 0, 1.0]]
+
+    def at(self, t):
+        w = 2 * np.pi * self.omega
+        xyz = self.base + math.sin(w * t) * self.mode
+        xyz_t = (w * math.cos(w * t)) * self.mode
+        return _grid(self.n, 2, xyz, self.off, xyz_t)
+
+
+def dpsl_ic(grid, gamma=5.0 / 3.0, M=0.1):
+    """Double periodic shear layer (Sec. 8.2): rho = 1 / (gamma M^2),
+    u = tanh(80 (y - 1/4)) for y <= 1/2 and tanh(80 (3/4 - y)) above,
+    v = 0.05 sin(2 pi (x + 1/4)), T = 1 (so p = rho T / (gamma M^2)) on the
+    unit square."""
+    x, y = grid["xyz"][0], grid["xyz"][1]
+    g = gamma * M * M
+    rho = np.full_like(x, 1.0 / g)
+    u = np.where(y <= 0.5, np.tanh(80.0 * (y - 0.25)), np.tanh(80.0 * (0.75 - y)))
+    v = 0.05 * np.sin(2 * np.pi * (x + 0.25))
+    p = rho * 1.0 / g
+    return conserved(rho, u, v, 0 * u, p, gamma, 2)
+
+
 def jet3d(n=(400, 180, 180), a_x=0.86, b_yz=0.325, skew=0.02):
     """Jet-shaped stretched periodic grid (synthetic stand-in for the paper's
     13 M-cell jet mesh of Sec. 8.3; the real mesh is not published).
