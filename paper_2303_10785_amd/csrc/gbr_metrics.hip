@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a, Ig4Metric
 }
 
 template <bool IG4>
-__global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4MetricStencil st)
+__global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4MetricStencil st, int fmask)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     if (idx >= a.dm.ncell) return;
@@ -176,6 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4Metric
     unpack(a.dm, idx, ijk);
     double *m = a.m;
     for (int f = 0; f < 3; ++f) {
+        if (!((fmask >> f) & 1)) continue;
         long nb[10];  // MEG6 window, reused by every slot
         if (!IG4)
             for (int q = -4; q <= 5; ++q) nb[q + 4] = step_to(a.dm, ijk, f, q, nullptr);
@@ -188,6 +189,63 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4Metric
         for (int e = 0; e < 3; ++e)
             for (int c = 0; c < 3; ++c)
                 m[GBR_SLOT_FACE_UNHAT(f, e, c) * N + idx] = interp(GBR_SLOT_CELL_UNHAT(e, c));
+    }
+}
+
+// MEG6 interface values of family F = 1 (eta) or 2 (zeta) from LDS tiles:
+// a workgroup owns FT interfaces along F for FC consecutive cells along i
+// and stages the 13 source slots of cells s0-4 .. s0+FT+4 once (each
+// interface's 10-point window then reads LDS instead of L2). Same formula on
+// the same values as k_face_metrics.
+constexpr int FT = 16, FC = kBlock / FT, FNP = FT + 9;
+
+template <int F>
+__global__ void __launch_bounds__(kBlock) k_face_metrics_tiled(MetricArgs a)
+{
+    constexpr int OD = (F == 1) ? 2 : 1;  // the remaining direction
+    __shared__ double sv[13][FNP * FC];
+    const Dims &dm = a.dm;
+    const long N = dm.ncell;
+    const int ns = dm.n[F], nc = dm.n[0];
+    const int tiles_s = (ns + FT - 1) / FT;
+    const int s0 = (blockIdx.x % tiles_s) * FT;
+    const int c0 = (blockIdx.x / tiles_s) * FC;
+    const int o = blockIdx.y;
+    int src[13];
+    for (int c = 0; c < 3; ++c) src[c] = GBR_SLOT_CELL_HAT(F, c);
+    src[3] = GBR_SLOT_CELL_HATT(F);
+    for (int e = 0; e < 3; ++e)
+        for (int c = 0; c < 3; ++c) src[4 + e * 3 + c] = GBR_SLOT_CELL_UNHAT(e, c);
+    for (int e = threadIdx.x; e < FNP * FC; e += kBlock) {
+        const int sl = e / FC, cl = e % FC;  // i fastest
+        int t[3];
+        t[0] = min(c0 + cl, nc - 1);
+        t[F] = wrap_index(s0 - 4 + sl, ns);
+        t[OD] = o;
+        const long cell = pack(dm, t[0], t[1], t[2]);
+#pragma unroll
+        for (int q = 0; q < 13; ++q) sv[q][e] = a.m[(long)src[q] * N + cell];
+    }
+    __syncthreads();
+    const int tl = threadIdx.x / FC, cl = threadIdx.x % FC;
+    const int sg = s0 + tl, cg = c0 + cl;
+    if (sg >= ns || cg >= nc) return;
+    int t[3];
+    t[0] = cg;
+    t[F] = sg;
+    t[OD] = o;
+    const long idx = pack(dm, t[0], t[1], t[2]);
+    int dst[13];
+    for (int c = 0; c < 3; ++c) dst[c] = GBR_SLOT_FACE_HAT(F, c);
+    dst[3] = GBR_SLOT_FACE_HATT(F);
+    for (int e = 0; e < 3; ++e)
+        for (int c = 0; c < 3; ++c) dst[4 + e * 3 + c] = GBR_SLOT_FACE_UNHAT(F, e, c);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        double v[10];
+#pragma unroll
+        for (int w = 0; w < 10; ++w) v[w] = sv[q][(tl + w) * FC + cl];  // cells sg-4 .. sg+5
+        a.m[(long)dst[q] * N + idx] = face_interp(v + 4);
     }
 }
 
@@ -329,10 +387,22 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
         hipLaunchKernelGGL(k_coord_deriv<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
         hipLaunchKernelGGL(k_cell_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
     }
-    if (g->cfg.scheme == GBR_SCHEME_MIG4)
-        hipLaunchKernelGGL(k_face_metrics<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
-    else
-        hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st);
+    if (g->cfg.scheme == GBR_SCHEME_MIG4) {
+        hipLaunchKernelGGL(k_face_metrics<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st, 7);
+    } else {
+        // xi family per cell (its windows lie along the wavefront's own rows);
+        // eta (and zeta in 3-D) from LDS tiles
+        const int n0 = a.dm.n[0];
+        hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st,
+                           a.ndim == 3 ? 1 : 5);
+        hipLaunchKernelGGL(k_face_metrics_tiled<1>,
+                           dim3(unsigned(((a.dm.n[1] + FT - 1) / FT) * ((n0 + FC - 1) / FC)), unsigned(a.dm.n[2])),
+                           dim3(kBlock), 0, g->stream, a);
+        if (a.ndim == 3)
+            hipLaunchKernelGGL(k_face_metrics_tiled<2>,
+                               dim3(unsigned(((a.dm.n[2] + FT - 1) / FT) * ((n0 + FC - 1) / FC)), unsigned(a.dm.n[1])),
+                               dim3(kBlock), 0, g->stream, a);
+    }
     hipLaunchKernelGGL(k_gcl, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     return hipGetLastError();
 }
