@@ -595,13 +595,9 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
         lo3[3 - T::SD - T::CD] = hi3[3 - T::SD - T::CD] = o;
         if (in_box(dm, lo3[0], lo3[1], lo3[2]) || in_box(dm, hi3[0], hi3[1], hi3[2])) atomicOr(a.flags, 1);
     }
-    __syncthreads();
-    // interface fluxes back to LDS (reusing the primitive buffer)
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sP[v * kBlock + T::at(t, cl, TS)] = phi[v];
-    __syncthreads();
-    // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7),
-    // with t and the cross lane of this thread's home position
+    // Phase-4 operands of the home cell s0+t (t and the cross lane of this
+    // thread's own position), issued before the flux exchange so that their
+    // latency overlaps it
     const int th = T::t_of(tid), clh = T::c_of(tid);
     const int cgh = c0 + clh;
     int h3[3];
@@ -609,19 +605,38 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     h3[T::CD] = cgh;
     h3[3 - T::SD - T::CD] = o;
     const bool interior = in_box(dm, h3[0], h3[1], h3[2]);
-    if (th < TS - 1 && s0 + th < ns && cgh < nc && (interior || MODE == 0)) {
-        const long ch = cell_of(dm, T::SD, T::CD, s0 + th, cgh, o);
-        double qnew[5];
-        double dt = 0.0, J = 0.0, it = 0.0, sg = 0.0, vj = 0.0;
-        if (MODE == 2) {
-            dt = *a.dt;
-            J = a.m[GBR_SLOT_CELL_J * N + ch];
-            it = a.m[GBR_SLOT_CELL_INVJT * N + ch];
-            if (a.sigma) {
-                sg = a.sigma[ch];
-                vj = a.m[GBR_SLOT_CELL_INVJ * N + ch];
-            }
+    const bool own = th < TS - 1 && s0 + th < ns && cgh < nc && (interior || MODE == 0);
+    const long ch = own ? cell_of(dm, T::SD, T::CD, s0 + th, cgh, o) : 0;
+    constexpr int NV = NDIM + 2;
+    R rold[NV];
+    double qin[NV], qn[NV];
+    double dt = 0.0, J = 0.0, it = 0.0, sg = 0.0, vj = 0.0;
+    if (own && MODE >= 1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) rold[v] = a.res[(long)v * N + ch];
+    }
+    if (own && MODE == 2) {
+        dt = *a.dt;
+        J = a.m[GBR_SLOT_CELL_J * N + ch];
+        it = a.m[GBR_SLOT_CELL_INVJT * N + ch];
+        if (a.sigma) {
+            sg = a.sigma[ch];
+            vj = a.m[GBR_SLOT_CELL_INVJ * N + ch];
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            qin[v] = a.Qin[(long)v * N + ch];
+            qn[v] = a.Qn[(long)v * N + ch];
+        }
+    }
+    __syncthreads();
+    // interface fluxes back to LDS (reusing the primitive buffer)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sP[v * kBlock + T::at(t, cl, TS)] = phi[v];
+    __syncthreads();
+    // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7)
+    if (own) {
+        double qnew[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
@@ -631,17 +646,17 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
             if (MODE == 0) {
                 *r = interior ? -d : R(0);  // Res is zero in ghost cells
             } else if (MODE == 1) {
-                *r = *r - d;
+                *r = rold[ov] - d;
             } else {
                 // App. B with Eq. time-split: Q <- a Qn + b (Q + dt J (Res - (1/J)_t Q)),
                 // Res with the sponge term -sigma (Q - Q_ref) / J (Sec. 8.3)
-                const R res = *r - d;
+                const R res = rold[ov] - d;
                 const long e = (long)ov * N + ch;
-                const double q = a.Qin[e];
+                const double q = qin[ov];
                 double rt = double(res);
                 if (a.sigma) rt -= sg * (q - a.qref[v]) * vj;
                 const double L = J * (rt - it * q);
-                qnew[ov] = a.ca * a.Qn[e] + a.cb * (q + dt * L);
+                qnew[ov] = a.ca * qn[ov] + a.cb * (q + dt * L);
                 a.Qout[e] = qnew[ov];
             }
         }
