@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_cfl(BatchArgs a)
 // cells along the interface normal; returns false for a non-physical state.
 template <bool LIM, class R>
 __device__ __forceinline__ bool face_flux_2d(const R *P, const R *G, int st, int vsP, int vsG, R nx, R ny,
-                                             R gamma, R gm1, R alpha_mp, R beta_mp, R phi[5])
+                                             R gamma, R igm1, R alpha_mp, R beta_mp, R phi[5])
 {
     R PL[5], PR[5];
     if (LIM)
@@ -127,7 +127,7 @@ __device__ __forceinline__ bool face_flux_2d(const R *P, const R *G, int st, int
         direct_states<4>(P, G, st, vsP, vsG, PL, PR);
     PL[3] = R(0);
     PR[3] = R(0);
-    hllc(PL, PR, R(0), nx, ny, R(0), gamma, gm1, phi);
+    hllc(PL, PR, R(0), nx, ny, R(0), gamma, igm1, phi);
     return PL[0] > R(0) && PL[4] > R(0) && PR[0] > R(0) && PR[4] > R(0) && isfinite(phi[0]) &&
            isfinite(phi[4]);
 }
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
     R *Gx = sG, *Gy = sG + 4 * VGX;
     R *Fx = sP, *Fy = sP + 4 * FX;  // fluxes, after the pencils are consumed
 
-    const R gamma = R(a.gamma), gm1 = R(a.gm1), amp = R(a.alpha_mp), bmp = R(a.beta_mp);
+    const R gamma = R(a.gamma), igm1 = R(1.0 / a.gm1), amp = R(a.alpha_mp), bmp = R(a.beta_mp);
     const int tid = threadIdx.x;
 
     for_items(a, [&](int2 it) {
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
             const R nx = R(G.m[GBR_SLOT_FACE_HAT(fam, 0) * N + ca]);
             const R ny = R(G.m[GBR_SLOT_FACE_HAT(fam, 1) * N + ca]);
             R ph[5];
-            const bool good = face_flux_2d<LIM>(P, Gd, st, vsP, vsG, nx, ny, gamma, gm1, amp, bmp, ph);
+            const bool good = face_flux_2d<LIM>(P, Gd, st, vsP, vsG, nx, ny, gamma, igm1, amp, bmp, ph);
             // only interfaces of cells inside the grid count
             const bool real = xi ? (j0 + fj < nj && i0 + fi - 1 < ni) : (i0 + fi < ni && j0 + fj - 1 < nj);
             ok = ok && (good || !real);

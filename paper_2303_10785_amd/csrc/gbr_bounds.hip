@@ -375,9 +375,10 @@ __global__ void __launch_bounds__(kBlock) k_bc_prims(Dims dm, Slab s, BcTypes bt
     if (type == GBR_BC_INFLOW) {
         // the caller's state in the ghost cell, as the primitives kernel forms it
         const double r = Q[gc];
-        const double u = Q[N + gc] / r;
-        const double v = Q[2 * N + gc] / r;
-        const double w = (NDIM == 3) ? Q[3 * N + gc] / r : 0.0;
+        const double ir = 1.0 / r;
+        const double u = Q[N + gc] * ir;
+        const double v = Q[2 * N + gc] * ir;
+        const double w = (NDIM == 3) ? Q[3 * N + gc] * ir : 0.0;
         const double E = Q[(NDIM + 1) * N + gc];
         const double p = gm1 * (E - 0.5 * r * (u * u + v * v + w * w));
         prim[gc] = R(r);
@@ -385,7 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_bc_prims(Dims dm, Slab s, BcTypes bt
         prim[2 * N + gc] = R(v);
         prim[3 * N + gc] = R(w);
         prim[4 * N + gc] = R(p);
-        prim[5 * N + gc] = R(gM2 * p / r);
+        prim[5 * N + gc] = R(gM2 * p * ir);
         return;
     }
     int src[3] = {t[0], t[1], t[2]};

@@ -96,17 +96,20 @@ __device__ __forceinline__ R mp_limit(R wm1, R w0, R wp1, R dm1, R d0, R dp1, R 
 template <class R>
 __device__ __forceinline__ R viscosity(R T, R suth, R re)
 {
-    return T * sqrt(T) * (R(1) + suth) / (T + suth) / re;
+    return T * sqrt(T) * (R(1) + suth) / ((T + suth) * re);
 }
 
 // Curvilinear HLLC flux of Sec. 5.1.1 for primitive states L, R and
-// interface metrics (nt, nx, ny, nz) = (hat xi_t, hat xi_x, hat xi_y, hat xi_z).
+// interface metrics (nt, nx, ny, nz) = (hat xi_t, hat xi_x, hat xi_y, hat xi_z);
+// igm1 = 1 / (gamma - 1).
 // One physical flux and at most one star state are formed: the selected side
-// K is L when S_L >= 0, R when S_R <= 0, else the side of S*. The wave speeds,
-// S* and the star state are evaluated in the order the paper prints them.
+// K is L when S_L >= 0, R when S_R <= 0, else the side of S*. The wave speeds
+// and S* are evaluated as the paper prints them; the star state uses the two
+// shared reciprocals 1 / |grad xi|^2 and 1 / (S_K - S*), which is the printed
+// expression with the factor rho_K (S_K - U_K) / (S_K - S*) multiplied in.
 template <class R>
 __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R ny, R nz, R gamma,
-                                     R gm1, R F[5])
+                                     R igm1, R F[5])
 {
     R nn = nx * nx + ny * ny + nz * nz;
     R sn = sqrt(nn);
@@ -125,18 +128,23 @@ __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R
     R U = useL ? UL : UR;
     R SK = useL ? SL : SR;
     R r = P[0], u = P[1], v = P[2], w = P[3], p = P[4];
-    R E = p / gm1 + R(0.5) * r * (u * u + v * v + w * w);
+    R E = p * igm1 + R(0.5) * r * (u * u + v * v + w * w);
     F[0] = r * U;
     F[1] = r * u * U + nx * p;
     F[2] = r * v * U + ny * p;
     F[3] = r * w * U + nz * p;
     F[4] = (E + p) * U - nt * p;
     if (star) {
-        R fac = r * (SK - U) / (SK - Ss);
-        R q1 = fac * (nx * (Ss - nt) + (ny * ny + nz * nz) * u - ny * nx * v - nz * nx * w) / nn;
-        R q2 = fac * (ny * (Ss - nt) - nx * ny * u + (nx * nx + nz * nz) * v - nz * ny * w) / nn;
-        R q3 = fac * (nz * (Ss - nt) - nx * nz * u - ny * nz * v + (nx * nx + ny * ny) * w) / nn;
-        R q4 = fac * (E / r + (Ss - U) * ((Ss - nt) / nn + p / (r * (SK - U))));
+        const R inn = R(1) / nn;
+        const R isk = R(1) / (SK - Ss);
+        const R d = SK - U;
+        const R fac = r * d * isk;
+        const R fn = fac * inn;
+        R q1 = fn * (nx * (Ss - nt) + (ny * ny + nz * nz) * u - ny * nx * v - nz * nx * w);
+        R q2 = fn * (ny * (Ss - nt) - nx * ny * u + (nx * nx + nz * nz) * v - nz * ny * w);
+        R q3 = fn * (nz * (Ss - nt) - nx * nz * u - ny * nz * v + (nx * nx + ny * ny) * w);
+        // fac (E / rho + (S* - U) ((S* - xi_t) / |grad xi|^2 + p / (rho (S_K - U))))
+        R q4 = isk * (d * E + (Ss - U) * p) + fn * (Ss - U) * (Ss - nt);
         F[0] += SK * (fac - r);
         F[1] += SK * (q1 - r * u);
         F[2] += SK * (q2 - r * v);

@@ -52,7 +52,7 @@ constexpr int kBlock = 256;
 
 template <class R>
 struct PhysR {
-    R gamma, gm1, gM2, suth, re, kden, theta_c, alpha_mp, beta_mp, alpha_d;
+    R gamma, igm1, gM2, suth, re, ikden, theta_c, alpha_mp, beta_mp, alpha_d;  // igm1 = 1 / gm1, ikden = 1 / kden
     int limiter;
 };
 
@@ -107,12 +107,13 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
     const long N = a.dm.ncell;
     if (idx >= N) return;
     double r = a.Q[idx];
-    double u = a.Q[N + idx] / r;
-    double v = a.Q[2 * N + idx] / r;
-    double w = (NDIM == 3) ? a.Q[3 * N + idx] / r : 0.0;
+    double ir = 1.0 / r;
+    double u = a.Q[N + idx] * ir;
+    double v = a.Q[2 * N + idx] * ir;
+    double w = (NDIM == 3) ? a.Q[3 * N + idx] * ir : 0.0;
     double E = a.Q[(NDIM + 1) * N + idx];
     double p = a.ph.gm1 * (E - 0.5 * r * (u * u + v * v + w * w));
-    double T = a.ph.gM2 * p / r;
+    double T = a.ph.gM2 * p * ir;
     a.prim[idx] = R(r);
     a.prim[N + idx] = R(u);
     a.prim[2 * N + idx] = R(v);
@@ -526,7 +527,7 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     const R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
     const R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
     R phi[5];
-    hllc(PL, PR, nt, nx, ny, nz, ph.gamma, ph.gm1, phi);
+    hllc(PL, PR, nt, nx, ny, nz, ph.gamma, ph.igm1, phi);
     if (VISC) {
         // Step-1: interface gradients of (u, v, w, T) along each computational
         // direction; the normal one from Eq. AD-eqn1 (beta_D = 0), tangential
@@ -566,7 +567,7 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
         R Tf = R(0.5) * (sL[3] + sR[3]);
         R mu = viscosity(Tf, ph.suth, ph.re);
         R lam = R(-2.0 / 3.0) * mu;
-        R kap = mu / ph.kden;
+        R kap = mu * ph.ikden;
         R uf = R(0.5) * (sL[0] + sR[0]), vf = R(0.5) * (sL[1] + sR[1]), wf = R(0.5) * (sL[2] + sR[2]);
         R div = Dx[0][0] + Dx[1][1] + Dx[2][2];
         R txx = R(2) * mu * Dx[0][0] + lam * div;
@@ -663,12 +664,13 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
         if (MODE == 2 && a.prim_out) {
             // primitives of the new state for the next stage (as k_prims)
             const double r = qnew[0];
-            const double u = qnew[1] / r;
-            const double v = qnew[2] / r;
-            const double w = (NDIM == 3) ? qnew[3] / r : 0.0;
+            const double ir = 1.0 / r;
+            const double u = qnew[1] * ir;
+            const double v = qnew[2] * ir;
+            const double w = (NDIM == 3) ? qnew[3] * ir : 0.0;
             const double E = qnew[NDIM + 1];
             const double p = a.ph.gm1 * (E - 0.5 * r * (u * u + v * v + w * w));
-            const double T = a.ph.gM2 * p / r;
+            const double T = a.ph.gM2 * p * ir;
             a.prim_out[ch] = R(r);
             a.prim_out[N + ch] = R(u);
             a.prim_out[2 * N + ch] = R(v);
@@ -962,7 +964,7 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.dm = dims_of(g);
     a.ph = phys_of(g);
     const Phys &p = a.ph;
-    a.pr = PhysR<R>{R(p.gamma), R(p.gm1), R(p.gM2), R(p.suth), R(p.re), R(p.kden),
+    a.pr = PhysR<R>{R(p.gamma), R(1.0 / p.gm1), R(p.gM2), R(p.suth), R(p.re), R(1.0 / p.kden),
                     R(p.theta_c), R(p.alpha_mp), R(p.beta_mp), R(p.alpha_d), p.limiter};
     a.Q = Q;
     a.res = res;
