@@ -352,11 +352,11 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
 // ----------------------------------------------------------------------------
 // per-direction interface sweep
 // ----------------------------------------------------------------------------
-template <int D>
+template <int D, int TSO = 0>
 struct Tile {
-    // faces per tile along D, lanes across, and index roles:
-    // s = sweep direction D, c = cross direction, o = outer direction.
-    static constexpr int TS = (D == 0) ? GBR_TS_XI : GBR_TS_CROSS;
+    // faces per tile along D (TSO overrides the default), lanes across, and
+    // index roles: s = sweep direction D, c = cross direction, o = outer direction.
+    static constexpr int TS = TSO ? TSO : ((D == 0) ? GBR_TS_XI : GBR_TS_CROSS);
     static constexpr int TC = kBlock / TS;
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
@@ -384,24 +384,24 @@ struct Tile {
 #define GBR_SWEEP_BOUNDS __launch_bounds__(kBlock, GBR_SWEEP_MINWAVES)
 // MODE: 0 writes Res, 1 adds to Res, 2 adds to Res and applies the SSP-RK3
 // stage to the tile's own cells (the last sweep of a gbr_step stage).
-template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R>
-__global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
+// One tile of TS - 1 cells along D: tile bx of a set of tiles_s tiles per
+// line, the first starting at cell s_begin. The LDS arrays come from the
+// kernel, sized for the largest tile shape it runs.
+template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R, int TSO>
+__device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int tiles_s, int bx, R *sP, R *s1,
+                                           R *s2, int *s_order, int *s_count)
 {
-    using T = Tile<D>;
+    using T = Tile<D, TSO>;
     constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, N2 = T::N2, st = T::ST;
     constexpr int VP = NP * TC, V1 = N1 * TC, V2 = N2 * TC;
-    __shared__ R sP[5 * VP];
-    __shared__ R s1[5 * V1];
-    __shared__ R s2[5 * V2];
 
     const Dims &dm = a.dm;
     const PhysR<R> &ph = a.pr;
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
-    const int tiles_s = (ns + TS - 2) / (TS - 1);
-    const int ts = blockIdx.x % tiles_s;
-    const int tcb = blockIdx.x / tiles_s;
-    const int s0 = ts * (TS - 1);
+    const int ts = bx % tiles_s;
+    const int tcb = bx / tiles_s;
+    const int s0 = s_begin + ts * (TS - 1);
     const int c0 = tcb * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
@@ -468,8 +468,6 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     // divergence they remove)
     constexpr bool compact = sizeof(R) == 8 && ((GBR_COMPACT_DIRS >> D) & 1);
     if (compact && ph.limiter == GBR_LIM_DUCROS) {
-        __shared__ int s_order[kBlock];
-        __shared__ int s_count[kBlock / 64];
         const int t0 = T::t_of(tid), cl0 = T::c_of(tid);
         const int cg0 = min(c0 + cl0, nc - 1);
         const long a0 = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t0 - 1, ns), cg0, o);
@@ -683,6 +681,29 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a)
     }
 }
 
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// A sweep launch: blocks [0, main_blocks) are tiles of the default shape,
+// tiles_s per line starting at cell 0; with TAIL > 0 the remaining blocks are
+// one TAIL-face tile per line starting at cell s_tail (the remainder of each
+// line), dispatched after the others so they fill the launch's drain.
+template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R, int TAIL>
+__global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a, int tiles_s, int main_blocks, int s_tail)
+{
+    using T0 = Tile<D>;
+    using T1 = Tile<D, TAIL ? TAIL : T0::TS>;
+    __shared__ R sP[5 * cmax(T0::NP * T0::TC, T1::NP * T1::TC)];
+    __shared__ R s1[5 * cmax(T0::N1 * T0::TC, T1::N1 * T1::TC)];
+    __shared__ R s2[5 * cmax(T0::N2 * T0::TC, T1::N2 * T1::TC)];
+    __shared__ int s_order[kBlock];
+    __shared__ int s_count[kBlock / 64];
+    if (TAIL == 0 || (int)blockIdx.x < main_blocks)
+        sweep_tile<D, NDIM, VISC, MODE, IG4, R, 0>(a, 0, tiles_s, blockIdx.x, sP, s1, s2, s_order, s_count);
+    else
+        sweep_tile<D, NDIM, VISC, MODE, IG4, R, TAIL>(a, s_tail, 1, blockIdx.x - main_blocks, sP, s1, s2, s_order,
+                                                      s_count);
+}
+
 // ----------------------------------------------------------------------------
 // SSP-RK3 stage (double accumulation) and time step
 // ----------------------------------------------------------------------------
@@ -762,21 +783,48 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
     if (e < n) d[e] = s[e];
 }
 
+template <int D, int NDIM, bool VISC, class R, bool IG4, int TAIL>
+void launch_sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode, int tiles_s, int s_tail)
+{
+    using T0 = Tile<D>;
+    using T1 = Tile<D, TAIL ? TAIL : T0::TS>;
+    const int nc = a.dm.n[T0::CD], no = a.dm.n[T0::OD];
+    const int main_blocks = tiles_s * ((nc + T0::TC - 1) / T0::TC);
+    const int tail_blocks = TAIL ? (nc + T1::TC - 1) / T1::TC : 0;
+    dim3 grid(unsigned(main_blocks + tail_blocks), unsigned(no));
+    if (mode == 0)
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, IG4, R, TAIL>), grid, dim3(kBlock), 0, g->stream, a, tiles_s,
+                           main_blocks, s_tail);
+    else if (mode == 1)
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, IG4, R, TAIL>), grid, dim3(kBlock), 0, g->stream, a, tiles_s,
+                           main_blocks, s_tail);
+    else
+        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, IG4, R, TAIL>), grid, dim3(kBlock), 0, g->stream, a, tiles_s,
+                           main_blocks, s_tail);
+}
+
+// xi lines are cut into tiles of GBR_TS_XI - 1 = 63 cells; a remainder of
+// fewer than GBR_TS_XI_TAIL cells goes to one narrow tile per line
+// (GBR_TS_XI_TAIL faces, kBlock / GBR_TS_XI_TAIL lines per workgroup) in the
+// same launch, so that few lanes idle (a 400-cell line: 6 tiles and 22 cells
+// in a 32-face tile, instead of 7 tiles with 41 idle lanes).
+#ifndef GBR_TS_XI_TAIL
+#define GBR_TS_XI_TAIL 32
+#endif
 template <int D, int NDIM, bool VISC, class R, bool IG4>
 hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode)
 {
     using T = Tile<D>;
-    const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
-    const int tiles_s = (ns + T::TS - 2) / (T::TS - 1);
-    const int tiles_c = (nc + T::TC - 1) / T::TC;
-    dim3 grid(unsigned(tiles_s * tiles_c), unsigned(no));
+    const int ns = a.dm.n[T::SD];
+    const int own = T::TS - 1, full = ns / own, rest = ns - full * own;
     Timed timed(g, GBR_K_SWEEP_XI + D);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 0, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
-    else if (mode == 1)
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 1, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
-    else
-        hipLaunchKernelGGL((k_sweep<D, NDIM, VISC, 2, IG4, R>), grid, dim3(kBlock), 0, g->stream, a);
+    if constexpr (D == 0 && GBR_TS_XI_TAIL > 0) {
+        if (rest > 0 && rest < GBR_TS_XI_TAIL) {
+            launch_sweep<D, NDIM, VISC, R, IG4, GBR_TS_XI_TAIL>(g, a, mode, full, full * own);
+            return hipGetLastError();
+        }
+    }
+    launch_sweep<D, NDIM, VISC, R, IG4, 0>(g, a, mode, full + (rest > 0 ? 1 : 0), 0);
     return hipGetLastError();
 }
 
