@@ -131,16 +131,22 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
 // (div^2 + |curl|^2 + 1e-30) of the physical velocity gradient
 // G[a][b] = sum_d (d_{x_b}) du_a/dd from the computational gradients gd[d][a].
 template <class R>
-__device__ __forceinline__ R ducros_theta(const R gd[3][4], const double *m, long N, long idx)
+__device__ __forceinline__ void load_unhat(const double *m, long N, long idx, R mt[3][3])
+{
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) mt[b][d] = R(m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx]);
+}
+
+template <class R>
+__device__ __forceinline__ R ducros_theta(const R gd[3][4], const R mt[3][3])
 {
     R G[3][3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        R mb[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) mb[d] = R(m[GBR_SLOT_CELL_UNHAT(d, b) * N + idx]);
-#pragma unroll
-        for (int aa = 0; aa < 3; ++aa) G[aa][b] = mb[0] * gd[0][aa] + mb[1] * gd[1][aa] + mb[2] * gd[2][aa];
+        for (int aa = 0; aa < 3; ++aa) G[aa][b] = mt[b][0] * gd[0][aa] + mt[b][1] * gd[1][aa] + mt[b][2] * gd[2][aa];
     }
     R div = G[0][0] + G[1][1] + G[2][2];
     R wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
@@ -248,7 +254,9 @@ __global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int q = 0; q < 4; ++q) gd[d][q] = (d < NDIM) ? a.grad[(d * 4 + q) * N + idx] : R(0);
-    a.theta[idx] = ducros_theta(gd, a.m, N, idx);
+    R mt[3][3];
+    load_unhat(a.m, N, idx, mt);
+    a.theta[idx] = ducros_theta(gd, mt);
 }
 
 // Gradient tile: GI x GJ cells in the (i, j) plane, marching KC planes along
@@ -301,6 +309,10 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
     }
     const int kend = min(k0 + KC, nk);
     for (int k = k0; k < kend; ++k) {
+        // the sensor's metrics are requested before the halo loads and the
+        // barrier, so their latency overlaps that work
+        R mt[3][3];
+        if (SENSOR) load_unhat(a.m, N, pack(dm, ic, jc, k), mt);
         if (NDIM == 3) {
             const long c = pack(dm, ic, jc, wrap_index(k + 3, nk));
 #pragma unroll
@@ -337,7 +349,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
-            if (SENSOR) a.theta[idx] = ducros_theta(gd, a.m, N, idx);
+            if (SENSOR) a.theta[idx] = ducros_theta(gd, mt);
         }
         __syncthreads();
         if (NDIM == 3) {
