@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_cfl(BatchArgs a)
         double best = __builtin_inf();
         if (i < G.ni && j < G.nj)
             best = cell_dt_bound<2, false>(G.Q, G.m, G.N, i + (long)G.ni * j, a.gamma, a.gm1, 0.0, 0.0, 1.0,
-                                           1.0);
+                                           1.0, false);  // batched grids are static
         for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
         if (threadIdx.x % warpSize == 0) wmin[threadIdx.x / warpSize] = best;
         __syncthreads();

@@ -156,10 +156,12 @@ __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R
 // Time-step bound of one cell (App. B): min over the directions d of
 // 1 / (|U_d| + c |grad d|) from the unhatted cell metrics, and, for viscous
 // flow, min_d 1 / (nu |grad d|^2) divided by alpha_D, with nu = mu / rho.
-// The step is dt = CFL * (minimum over all cells).
+// The step is dt = CFL * (minimum over all cells). The temporal metrics are
+// read only on moving grids (they are zero on static ones).
 template <int NDIM, bool VISC>
 __device__ __forceinline__ double cell_dt_bound(const double *Q, const double *m, long N, long idx, double gamma,
-                                                double gm1, double gM2, double suth, double re, double alpha_d)
+                                                double gm1, double gM2, double suth, double re, double alpha_d,
+                                                bool moving)
 {
     double r = Q[idx];
     double u = Q[N + idx] / r, v = Q[2 * N + idx] / r;
@@ -173,7 +175,7 @@ __device__ __forceinline__ double cell_dt_bound(const double *Q, const double *m
         double dx = m[GBR_SLOT_CELL_UNHAT(d, 0) * N + idx];
         double dy = m[GBR_SLOT_CELL_UNHAT(d, 1) * N + idx];
         double dz = m[GBR_SLOT_CELL_UNHAT(d, 2) * N + idx];
-        double U = m[GBR_SLOT_CELL_UNHATT(d) * N + idx] + dx * u + dy * v + dz * w;
+        double U = (moving ? m[GBR_SLOT_CELL_UNHATT(d) * N + idx] : 0.0) + dx * u + dy * v + dz * w;
         double g2 = dx * dx + dy * dy + dz * dz;
         best = fmin(best, 1.0 / (fabs(U) + c * sqrt(g2)));
         if (VISC) bv = fmin(bv, 1.0 / (nu * g2));

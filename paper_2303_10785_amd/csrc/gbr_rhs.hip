@@ -744,14 +744,14 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Dims dm, long ncell, double
 // Per-block minimum of the admissible step over a grid-stride range of cells.
 template <int NDIM, bool VISC>
 __global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const double *Q, const double *m,
-                                                          double *partial)
+                                                          int moving, double *partial)
 {
     const long N = dm.ncell;
     double best = __builtin_inf();
     for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
         if (!in_box(dm, idx)) continue;  // ghost cells are not advanced
         best = fmin(best, cell_dt_bound<NDIM, VISC>(Q, m, N, idx, ph.gamma, ph.gm1, ph.gM2, ph.suth, ph.re,
-                                                        ph.alpha_d));
+                                                        ph.alpha_d, moving != 0));
     }
     // wavefront minimum, then across the block's wavefronts
     for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
@@ -1189,17 +1189,17 @@ hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
     if (g->cfg.ndim == 3) {
         if (visc)
             hipLaunchKernelGGL((k_cfl_partial<3, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->partial);
+                               g->metrics, g->cfg.moving, g->partial);
         else
             hipLaunchKernelGGL((k_cfl_partial<3, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->partial);
+                               g->metrics, g->cfg.moving, g->partial);
     } else {
         if (visc)
             hipLaunchKernelGGL((k_cfl_partial<2, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->partial);
+                               g->metrics, g->cfg.moving, g->partial);
         else
             hipLaunchKernelGGL((k_cfl_partial<2, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->partial);
+                               g->metrics, g->cfg.moving, g->partial);
     }
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, g->partial, blocks, cfl, dt);
     return hipGetLastError();

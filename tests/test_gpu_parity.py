@@ -356,3 +356,40 @@ def test_fp32_bulk_freestream_moving(gbr):
     say(f"[fp32 freestream] max |v|,|w| after 10 moving steps {vmax:.3e}")
     h.close()
     assert vmax < 1e-5
+
+
+# xi line lengths around the sweep's tiling: lines are cut into 63-cell
+# tiles and a remainder below 32 cells goes to a 32-face tail tile in the
+# same launch. 31: tail only; 32: one partial full tile; 63: one exact tile;
+# 64: a tile and a 1-cell tail; 94: a tile and the largest tail (31);
+# 95: two tiles, the second partial; 126: two exact tiles.
+XI_LENGTHS = [31, 32, 63, 64, 94, 95, 126]
+
+
+@pytest.mark.parametrize("ni", XI_LENGTHS)
+def test_xi_tiling_rhs_and_steps(gbr, ni):
+    """One RHS and two SSP-RK3 steps (the last xi sweep of each stage applies
+    the stage and forms the next primitives) match the oracle on an
+    ni x 5 x 4 randomized grid with a rough state, NS with the Ducros gate."""
+    g = W.random3d((ni, 5, 4), amp=0.1, seed=20 + ni)
+    Q = W.random_rough_state(g, seed=30 + ni)
+    params = dict(viscous=True, limiter="ducros", theta_c=0.2, Re=100.0)
+    say(f"[xi tiling] ni={ni} n={g['n']}")
+    h = gbr.Grid(g, **params)
+    h.metrics(dev(g["xyz"]))
+    m = oracle.metrics(g, **params)
+    Qd = dev(Q)
+    res = torch.empty_like(Qd)
+    h.rhs(Qd, res)
+    torch.cuda.synchronize()
+    e_rhs = rel(res.cpu().numpy(), oracle.rhs(g, m, Q, **params))
+    dt = 2e-4
+    for s in range(2):
+        h.step(Qd, dt, gbr.GBR_DT_FIXED)
+        Q, _ = oracle.step(g, m, Q, dt, dt_mode=oracle.DT_FIXED, **params)
+    torch.cuda.synchronize()
+    e_step = rel(Qd.cpu().numpy(), Q)
+    say(f"[xi tiling] ni={ni}: rhs max rel err {e_rhs:.3e}, state after 2 steps {e_step:.3e}")
+    assert h.check_state() == gbr.GBR_OK
+    h.close()
+    assert e_rhs <= TOL and e_step <= TOL
