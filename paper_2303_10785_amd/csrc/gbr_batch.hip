@@ -162,8 +162,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
 
         auto prim = [&](long c, R *dst, int vs) {
             double r = in[c];
-            double u = in[N + c] / r;
-            double v = in[2 * N + c] / r;
+            double ir = 1.0 / r;  // as the single-grid primitives kernel
+            double u = in[N + c] * ir;
+            double v = in[2 * N + c] * ir;
             double w = 0.0;
             double p = a.gm1 * (in[3 * N + c] - 0.5 * r * (u * u + v * v + w * w));
             dst[0] = R(r);
@@ -261,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
 #pragma unroll
             for (int v = 0; v < 4; ++v) q[v] = in[v * N + c];
             {
-                double r = q[0], u = q[1] / r, v = q[2] / r;
+                double r = q[0], ir = 1.0 / r, u = q[1] * ir, v = q[2] * ir;
                 double p = a.gm1 * (q[3] - 0.5 * r * (u * u + v * v));
                 if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v)))
                     atomicOr(G.flags, 1);
