@@ -418,7 +418,10 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
 
-    // Phase 1: primitives of cells s0-6 .. s0+TS+4 into LDS
+    // Phase 1: primitives of cells s0-6 .. s0+TS+4 into LDS. The wave's issue
+    // priority is raised while it requests them, so that a new tile's loads
+    // go out ahead of the arithmetic of the other tiles on the SIMD.
+    __builtin_amdgcn_s_setprio(2);
     for (int e = tid; e < VP; e += kBlock) {
         int sl = (D == 0) ? e % NP : e / TC;
         int cl = (D == 0) ? e / NP : e % TC;
@@ -429,6 +432,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
 #pragma unroll
         for (int v = 0; v < 5; ++v) sP[v * VP + at] = a.prim[v * N + c];
     }
+    __builtin_amdgcn_s_setprio(0);
     __syncthreads();
     // Phase 2: first derivatives of cells s0-3 .. s0+TS+1: E6 from the LDS
     // pencils (MEG6), or the stored IG4 gradients (MIG4)
