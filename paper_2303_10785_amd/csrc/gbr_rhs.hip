@@ -171,16 +171,25 @@ struct Ig4Tile {
     static constexpr int CD = (D == 0) ? 1 : 0;
     static constexpr int OD = (D == 2) ? 1 : 2;
     static constexpr int LEN = TS + 2 * kIg4Half;
-    // LDS position of (s, c): along s contiguous for xi, c contiguous otherwise
-    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * LEN + sl : sl * TC + cl; }
-    static constexpr int ST = (D == 0) ? 1 : TC;
+    static_assert(D != 0 || LEN % 4 == 0, "xi lines are stored in four quarter-rows");
+    // LDS position of (s, c). Along eta / zeta c is contiguous. Along xi a
+    // thread owns cells 4 sq .. 4 sq + 3, so cell s of a line sits in
+    // quarter-row s % 4 at position s / 4: for every window read the 64 lanes
+    // of a wavefront then touch consecutive words (plain rows would put them
+    // 32 bytes apart, an 8-way bank conflict).
+    __device__ static constexpr int at(int sl, int cl)
+    {
+        return D == 0 ? cl * LEN + (sl & 3) * (LEN / 4) + (sl >> 2) : sl * TC + cl;
+    }
+    // offset of cell 4 sq + k from cell 4 sq of the same line (k >= 0)
+    __device__ static constexpr int off(int k) { return D == 0 ? (k & 3) * (LEN / 4) + (k >> 2) : k * TC; }
 };
 
 template <int D, int NDIM, class R>
 __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st)
 {
     using T = Ig4Tile<D>;
-    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN, ST = T::ST;
+    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN;
     static_assert(TC * (TS / 4) == kBlock, "four cells per thread");
     __shared__ R buf[LEN * TC];
     const Dims &dm = a.dm;
@@ -209,12 +218,12 @@ __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st
             __syncthreads();
             // sliding windows: at step j, P[q] = f(4 sq + q + j) and
             // M[q] = f(4 sq + q - j); each step loads one new value per side
-            const R *c = buf + T::at(4 * sq + H, cl);
+            const R *c = buf + T::at(4 * sq, cl);  // cell 4 sq + k at c[T::off(k)]
             R P[4], M[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                P[q] = c[(q + 1) * ST];
-                M[q] = c[(q - 1) * ST];
+                P[q] = c[T::off(H + q + 1)];
+                M[q] = c[T::off(H + q - 1)];
             }
 #pragma unroll GBR_IG4_UNROLL
             for (int j = 1; j <= H; ++j) {
@@ -225,11 +234,11 @@ __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st
                     P[0] = P[1];
                     P[1] = P[2];
                     P[2] = P[3];
-                    P[3] = c[(4 + j) * ST];
+                    P[3] = c[T::off(H + 4 + j)];
                     M[3] = M[2];
                     M[2] = M[1];
                     M[1] = M[0];
-                    M[0] = c[(-1 - j) * ST];
+                    M[0] = c[T::off(H - 1 - j)];
                 }
             }
             __syncthreads();
