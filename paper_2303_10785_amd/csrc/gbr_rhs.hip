@@ -492,6 +492,8 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     // (FP64 only: in FP32 the scattered LDS reads cost more than the
     // divergence they remove)
     constexpr bool compact = sizeof(R) == 8 && ((GBR_COMPACT_DIRS >> D) & 1);
+    // raised issue priority for the sensor loads of the gather, as in phase 1
+    __builtin_amdgcn_s_setprio(2);
     if (compact && ph.limiter == GBR_LIM_DUCROS) {
         const int t0 = T::t_of(tid), cl0 = T::c_of(tid);
         const int cg0 = min(c0 + cl0, nc - 1);
@@ -515,6 +517,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         f = s_order[tid];
         limited = tid < total;
     }
+    __builtin_amdgcn_s_setprio(0);
     const int t = T::t_of(f);
     const int cl = T::c_of(f);
     const int cg = c0 + cl;
