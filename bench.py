@@ -49,7 +49,8 @@ ALG_BYTES_PER_CELL = {
     # stage's primitives out in two of the three stages
     "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40 + 96 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
-    "cfl": 40 + 72,                       # Q, 9 cell metrics (the temporal ones: moving grids only)
+    # gbr_step forms the first stage's primitives in the time-step pass
+    "cfl": 40 + 72 + 48,                  # Q, 9 cell metrics (temporal ones: moving grids only) -> primitives
 }
 
 

@@ -262,7 +262,8 @@ enum {
     GBR_K_SWEEP_ETA = 3,   /* interface sweep along eta                          */
     GBR_K_SWEEP_ZETA = 4,  /* interface sweep along zeta                         */
     GBR_K_RK_STAGE = 5,    /* SSP-RK3 stage update                               */
-    GBR_K_CFL = 6,         /* time-step reduction                                */
+    GBR_K_CFL = 6,         /* time-step reduction (in gbr_step fused with the
+                              first stage's primitives)                          */
     GBR_K_COPY = 7,        /* state copies and fills                             */
     GBR_K_PRIMS = 8,       /* primitive variables of the state                   */
     GBR_K_DIAG = 9,        /* diagnostics                                        */

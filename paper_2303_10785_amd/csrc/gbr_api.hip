@@ -358,11 +358,13 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
         }
         if (e == hipSuccess) {
             if (dt_mode == GBR_DT_CFL)
-                e = gbr::launch_cfl(gg, Q[b], cfl_or_dt, gg->dt);
+                e = gbr::launch_cfl_prims(gg, Q[b], cfl_or_dt, gg->dt);
             else
                 e = gbr::launch_fill(gg, gg->dt, 1, cfl_or_dt);
         }
-        for (int st = 0; st < 3 && e == hipSuccess; ++st) e = gbr::launch_step_stage(gg, st, gg->dt, Q[b], gg->qn);
+        const bool prims_ready = dt_mode == GBR_DT_CFL;
+        for (int st = 0; st < 3 && e == hipSuccess; ++st)
+            e = gbr::launch_step_stage(gg, st, gg->dt, Q[b], gg->qn, st == 0 && prims_ready);
         if (e == hipSuccess && gg->bounded) e = gbr::launch_bc_state(gg, Q[b]);
         if (e == hipSuccess && dt_out && dt_out[b]) e = gbr::launch_copy(gg, dt_out[b], gg->dt, 1);
         if (e != hipSuccess) return hip_fail(gg, e, "step launch");

@@ -123,8 +123,12 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
 hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, double *integrals);
 // RHS and SSP-RK3 stage of gbr_step with the stage fused into the last sweep.
 // Q: state at the start of the step, advanced in place; S: stage buffer.
-hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S);
+// prims_ready: the first stage's primitives were formed by launch_cfl_prims.
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S,
+                             bool prims_ready = false);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
+// launch_cfl plus the primitives of Q for the first stage of gbr_step.
+hipError_t launch_cfl_prims(gbr_grid_s *g, const double *Q, double cfl, double *dt);
 // Non-periodic boundaries (gbr_bounds.hip): App. C metrics of a static grid
 // with ghost slots copied from the nearest interior ones; ghost primitives
 // from the boundary types (Dirichlet ghosts from Q's own ghost cells); ghost

@@ -101,11 +101,9 @@ __device__ __forceinline__ long cell_of(const Dims &dm, int sd, int cd, int s, i
 // primitives, cell gradients and sensor
 // ----------------------------------------------------------------------------
 template <int NDIM, class R>
-__global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
+__device__ __forceinline__ void prims_cell(const RhsArgs<R> &a, long idx)
 {
-    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
     const long N = a.dm.ncell;
-    if (idx >= N) return;
     double r = a.Q[idx];
     double ir = 1.0 / r;
     double u = a.Q[N + idx] * ir;
@@ -125,6 +123,13 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
     if (!(r > 0.0 && p > 0.0 && isfinite(r) && isfinite(p) && isfinite(u) && isfinite(v) && isfinite(w)) &&
         in_box(a.dm, idx))
         atomicOr(a.flags, 1);
+}
+
+template <int NDIM, class R>
+__global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
+{
+    long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx < a.dm.ncell) prims_cell<NDIM, R>(a, idx);
 }
 
 // Ducros sensor (builder-defined gate of the limiter): theta = div^2 /
@@ -757,6 +762,21 @@ __global__ void __launch_bounds__(kBlock) k_rk_stage(Dims dm, long ncell, double
     }
 }
 
+// Minimum of best over the block (wavefronts first) into partial[blockIdx.x].
+__device__ __forceinline__ void block_min_to(double best, double *partial)
+{
+    for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
+    __shared__ double wmin[kBlock / 32];
+    const int lane = threadIdx.x % warpSize, wave = threadIdx.x / warpSize;
+    if (lane == 0) wmin[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = wmin[0];
+        for (int q = 1; q < kBlock / warpSize; ++q) b = fmin(b, wmin[q]);
+        partial[blockIdx.x] = b;
+    }
+}
+
 // Per-block minimum of the admissible step over a grid-stride range of cells.
 template <int NDIM, bool VISC>
 __global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const double *Q, const double *m,
@@ -769,17 +789,24 @@ __global__ void __launch_bounds__(kBlock) k_cfl_partial(Dims dm, Phys ph, const 
         best = fmin(best, cell_dt_bound<NDIM, VISC>(Q, m, N, idx, ph.gamma, ph.gm1, ph.gM2, ph.suth, ph.re,
                                                         ph.alpha_d, moving != 0));
     }
-    // wavefront minimum, then across the block's wavefronts
-    for (int off = warpSize / 2; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off));
-    __shared__ double wmin[kBlock / 32];
-    const int lane = threadIdx.x % warpSize, wave = threadIdx.x / warpSize;
-    if (lane == 0) wmin[wave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double b = wmin[0];
-        for (int q = 1; q < kBlock / warpSize; ++q) b = fmin(b, wmin[q]);
-        partial[blockIdx.x] = b;
+    block_min_to(best, partial);
+}
+
+// The same minimum fused with the primitives of the step's first stage
+// (k_prims): both read Q at the start of a step, so one pass serves both.
+template <int NDIM, bool VISC, class R>
+__global__ void __launch_bounds__(kBlock) k_prims_cfl(RhsArgs<R> a, int moving, double *partial)
+{
+    const long N = a.dm.ncell;
+    const Phys &ph = a.ph;
+    double best = __builtin_inf();
+    for (long idx = blockIdx.x * (long)kBlock + threadIdx.x; idx < N; idx += (long)gridDim.x * kBlock) {
+        prims_cell<NDIM, R>(a, idx);
+        if (!in_box(a.dm, idx)) continue;  // ghost cells are not advanced
+        best = fmin(best, cell_dt_bound<NDIM, VISC>(a.Q, a.m, N, idx, ph.gamma, ph.gm1, ph.gM2, ph.suth, ph.re,
+                                                        ph.alpha_d, moving != 0));
     }
+    block_min_to(best, partial);
 }
 
 // Minimum of the per-block values; dt = cfl * min.
@@ -1130,7 +1157,7 @@ static const double kRkB[3] = {1.0, 0.25, 2.0 / 3.0};
 // buffer of its index parity and the fused last sweep writes the next
 // stage's primitives into the other one.
 template <class R>
-hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S)
+hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S, bool prims_ready)
 {
     RhsArgs<R> a = make_args<R>(g, Q, static_cast<R *>(static_cast<void *>(g->res)));
     R *buf[2] = {reinterpret_cast<R *>(g->prim), reinterpret_cast<R *>(g->prim2)};
@@ -1142,7 +1169,7 @@ hipError_t step_stage_typed(gbr_grid_s *g, int stage, const double *dt, double *
     a.dt = dt;
     a.ca = kRkA[stage];
     a.cb = kRkB[stage];
-    const bool visc = g->cfg.viscous != 0, first = stage == 0;
+    const bool visc = g->cfg.viscous != 0, first = stage == 0 && !prims_ready;
     if (g->cfg.ndim == 3)
         return visc ? rhs_all<3, true, R>(g, a, first, true) : rhs_all<3, false, R>(g, a, first, true);
     return visc ? rhs_all<2, true, R>(g, a, first, true) : rhs_all<2, false, R>(g, a, first, true);
@@ -1180,10 +1207,10 @@ hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, do
     return diag_typed<double>(g, Q, fields, integrals);
 }
 
-hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S)
+hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S, bool prims_ready)
 {
-    if (g->cfg.precision == GBR_FP32_BULK) return step_stage_typed<float>(g, stage, dt, Q, S);
-    return step_stage_typed<double>(g, stage, dt, Q, S);
+    if (g->cfg.precision == GBR_FP32_BULK) return step_stage_typed<float>(g, stage, dt, Q, S, prims_ready);
+    return step_stage_typed<double>(g, stage, dt, Q, S, prims_ready);
 }
 
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn, double *Q,
@@ -1219,6 +1246,37 @@ hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
     }
     hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, g->partial, blocks, cfl, dt);
     return hipGetLastError();
+}
+
+namespace {
+template <class R>
+hipError_t cfl_prims_typed(gbr_grid_s *g, const double *Q, double cfl, double *dt)
+{
+    RhsArgs<R> a = make_args<R>(g, Q, nullptr);  // a.prim: the first stage's buffer
+    long want = (g->ncell + kBlock - 1) / kBlock;
+    int blocks = int(want < kReducePartials ? want : kReducePartials);
+    const int mv = g->cfg.moving;
+    Timed timed(g, GBR_K_CFL);
+    if (g->cfg.ndim == 3) {
+        if (g->cfg.viscous)
+            hipLaunchKernelGGL((k_prims_cfl<3, true, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, mv, g->partial);
+        else
+            hipLaunchKernelGGL((k_prims_cfl<3, false, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, mv, g->partial);
+    } else {
+        if (g->cfg.viscous)
+            hipLaunchKernelGGL((k_prims_cfl<2, true, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, mv, g->partial);
+        else
+            hipLaunchKernelGGL((k_prims_cfl<2, false, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a, mv, g->partial);
+    }
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, g->partial, blocks, cfl, dt);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_cfl_prims(gbr_grid_s *g, const double *Q, double cfl, double *dt)
+{
+    if (g->cfg.precision == GBR_FP32_BULK) return cfl_prims_typed<float>(g, Q, cfl, dt);
+    return cfl_prims_typed<double>(g, Q, cfl, dt);
 }
 
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value)
