@@ -346,24 +346,24 @@ __device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const
         WL[v] = mp_limit(w[0], w[1], w[2], d[0], d[1], d[2], wl, alpha_mp, beta_mp);
         WR[v] = mp_limit(w[3], w[2], w[1], d[3], d[2], d[1], wr, alpha_mp, beta_mp);
     };
-    {
-        // W0 = p - ra (e.u), W4 = p + ra (e.u)
-        R w0[4], w4[4], d0[4], d4[4], g0[2], g4[2];
-        auto acoustic = [&](const R *x, int vs, int o, R &m, R &p) {
+    // W0 = p - ra (e.u), W4 = p + ra (e.u), one field at a time (fewer live
+    // registers at the limiter's peak; the pencils are read twice from LDS)
+#pragma unroll
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+        R w[4], d[4], g[2];
+        auto acoustic = [&](const R *x, int vs, int o) {
             R un = ex * ld(x, vs, 1, o) + ey * ld(x, vs, 2, o) + ez * ld(x, vs, 3, o);
             R x4 = ld(x, vs, 4, o);
-            m = x4 - ra * un;
-            p = x4 + ra * un;
+            return sgn < 0 ? x4 - ra * un : x4 + ra * un;
         };
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            acoustic(P, vsP, (k - 1) * ST, w0[k], w4[k]);
-            acoustic(H, vsH, (k - 1) * ST, d0[k], d4[k]);
+            w[k] = acoustic(P, vsP, (k - 1) * ST);
+            d[k] = acoustic(H, vsH, (k - 1) * ST);
         }
 #pragma unroll
-        for (int k = 0; k < 2; ++k) acoustic(G, vsG, k * ST, g0[k], g4[k]);
-        limit(0, w0, d0, g0);
-        limit(4, w4, d4, g4);
+        for (int k = 0; k < 2; ++k) g[k] = acoustic(G, vsG, k * ST);
+        limit(sgn < 0 ? 0 : 4, w, d, g);
     }
     // W1 = ex s + (ey w - ez v), W2 = ez s + (ex v - ey u),
     // W3 = -ey s - (ez u - ex w), s = a^2 rho - p

@@ -534,17 +534,37 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const R *Ha = s2 + T::at(t + 1, cl, N2);
     const double *m = a.m;
     if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
+    // In the eta and zeta sweeps the interface metrics are requested before
+    // the unlimited states are formed, so their latency overlaps that work
+    // (the limited path reads them after the limiter, whose register peak
+    // they would raise). The xi sweep, which carries the RK stage, has no
+    // registers to spare for that and reads them after both paths.
+    constexpr bool pre = D != 0;
+    const R *gr = a.grad;
+    const R *Tc = a.prim + 5 * N;
+    R nt, nx, ny, nz;
+    auto load_face = [&]() {
+        nt = a.moving ? R(m[GBR_SLOT_FACE_HATT(D) * N + ca]) : R(0);
+        nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
+        ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
+        nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
+    };
     R PL[5], PR[5];
     if (limited) {
-        // the normal is read here and again for the flux: keeping it live
-        // across the limiter costs a wave of occupancy in FP64
-        R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
-        R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
-        R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
-        limited_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, nx, ny, nz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
+        {
+            // the normal is read here and again for the flux: keeping it live
+            // across the limiter costs a wave of occupancy in FP64
+            R lx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
+            R ly = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
+            R lz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
+            limited_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, lx, ly, lz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
+        }
+        if (pre) load_face();
     } else {
+        if (pre) load_face();
         direct_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, PL, PR);
     }
+    if (!pre) load_face();
     if (NDIM == 2) {
         PL[3] = R(0);
         PR[3] = R(0);
@@ -553,18 +573,12 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
 
     // HLLC (Step-6) and the alpha-damping viscous flux (Sec. 5.2); the
     // temporal metric is zero on static grids and not read there
-    const R nt = a.moving ? R(m[GBR_SLOT_FACE_HATT(D) * N + ca]) : R(0);
-    const R nx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
-    const R ny = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
-    const R nz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
     R phi[5];
     hllc(PL, PR, nt, nx, ny, nz, ph.gamma, ph.igm1, phi);
     if (VISC) {
         // Step-1: interface gradients of (u, v, w, T) along each computational
         // direction; the normal one from Eq. AD-eqn1 (beta_D = 0), tangential
         // ones from the average of the two cell gradients.
-        const R *gr = a.grad;
-        const R *Tc = a.prim + 5 * N;
         R c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], Tc[ca]};
         R c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], Tc[cb]};
         R g0[4] = {Ga[V1], Ga[2 * V1], Ga[3 * V1], gr[(D * 4 + 3) * N + ca]};
