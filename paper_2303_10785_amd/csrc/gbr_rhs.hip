@@ -132,7 +132,8 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
     if (idx < a.dm.ncell) prims_cell<NDIM, R>(a, idx);
 }
 
-// Ducros sensor (builder-defined gate of the limiter): theta = div^2 /
+// Ducros sensor (a gate of the limiter added by this implementation, not in
+// the paper): theta = div^2 /
 // (div^2 + |curl|^2 + 1e-30) of the physical velocity gradient
 // G[a][b] = sum_d (d_{x_b}) du_a/dd from the computational gradients gd[d][a].
 template <class R>
