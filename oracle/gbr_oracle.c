@@ -492,9 +492,13 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
  * Jac-matrix, Jacb2) with D_d = difference of interface values built on IG4
  * gradients (Eq. FP-interp, FP-interp2 with Eq. IG4_grads, as the paper
  * directs for MIG4), and the interface values of the metrics from the same
- * IG4 interpolation. The IG4 system couples a whole line, so lines are
- * processed whole, in the coordinates as given.
- * Pins: discrete metric identities, freestream, convergence of the metrics. */
+ * IG4 interpolation. The IG4 system couples a whole line; the derivatives
+ * of coordinates and coordinate products are taken, as in ref_metrics, with
+ * the coordinate measured from the target cell (the metrics are invariant
+ * under a translation), one line per target cell, with the inverse of the
+ * cyclic IG4 matrix formed once per line length.
+ * Pins: discrete metric identities, freestream, convergence of the metrics,
+ * translation invariance.                                                  */
 typedef struct {
     const ref_cfg *g;
     int d;              /* line direction                                  */
@@ -536,18 +540,124 @@ static int line_job_fn(void *ctx, const long *cells)
 
 static int run_job(line_job jb) { return for_lines(jb.g, jb.d, line_job_fn, &jb); }
 
+/* Inverse of the cyclic IG4 matrix of order n (1 on the diagonal, alpha on
+ * the two neighbours, cyclically: the left-hand side of Eq. IG4_grads on a
+ * periodic line), row-major, by Gauss-Jordan elimination with partial
+ * pivoting. NULL on allocation failure or a singular matrix.              */
+static double *ig4_inverse(int n)
+{
+    double *A = (double *)calloc((size_t)n * n, sizeof(double));
+    double *X = (double *)calloc((size_t)n * n, sizeof(double));
+    if (!A || !X) { free(A); free(X); return NULL; }
+    for (int k = 0; k < n; ++k) {
+        A[k * n + k] += 1.0;
+        A[k * n + mod_n(k - 1, n)] += ig4_alpha;
+        A[k * n + mod_n(k + 1, n)] += ig4_alpha;
+        X[k * n + k] = 1.0;
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int k = c + 1; k < n; ++k)
+            if (fabs(A[k * n + c]) > fabs(A[piv * n + c])) piv = k;
+        if (A[piv * n + c] == 0.0) { free(A); free(X); return NULL; }
+        if (piv != c)
+            for (int q = 0; q < n; ++q) {
+                double t = A[c * n + q]; A[c * n + q] = A[piv * n + q]; A[piv * n + q] = t;
+                t = X[c * n + q]; X[c * n + q] = X[piv * n + q]; X[piv * n + q] = t;
+            }
+        double p = A[c * n + c];
+        for (int q = 0; q < n; ++q) { A[c * n + q] /= p; X[c * n + q] /= p; }
+        for (int k = 0; k < n; ++k) {
+            if (k == c) continue;
+            double f = A[k * n + c];
+            if (f == 0.0) continue;
+            for (int q = 0; q < n; ++q) { A[k * n + q] -= f * A[c * n + q]; X[k * n + q] -= f * X[c * n + q]; }
+        }
+    }
+    free(A);
+    return X;
+}
+
+/* D_d of the line F = fac * x (fac NULL: 1) at every cell i, with x measured
+ * from cell i: Eq. FP-interp2 applied to G(m) = fac_m ((x_m + w off) - x_i),
+ * w the number of periods the index m crossed (the periodic image is formed
+ * first, then shifted, as in ref_metrics). G extends with the jump
+ * fac * off per period, so its IG4 derivative (Eq. IG4_grads) is that of
+ * ig4_ext, here y = Ainv (r - jump rows) + w dj with dj = IG4 of the jump
+ * line; the interface values at i -+ 1/2 follow ig4_faces.               */
+typedef struct {
+    const ref_cfg *g;
+    int d;
+    const double *fac, *xc;
+    double jump;
+    double *out;
+    const double *ainv;   /* inverse of the cyclic IG4 matrix of order n[d] */
+} dloc_job;
+
+static int dloc_fn(void *ctx, const long *cells)
+{
+    dloc_job *jb = (dloc_job *)ctx;
+    const int n = jb->g->n[jb->d];
+    double *fa = (double *)malloc(sizeof(double) * n);
+    double *x = (double *)malloc(sizeof(double) * n);
+    double *J = (double *)calloc((size_t)n, sizeof(double));
+    double *dj = (double *)malloc(sizeof(double) * n);
+    double *r = (double *)malloc(sizeof(double) * n);
+    int rc = (!fa || !x || !J || !dj || !r) ? -1 : 0;
+    if (!rc) {
+        for (int k = 0; k < n; ++k) {
+            fa[k] = jb->fac ? jb->fac[cells[k]] : 1.0;
+            x[k] = jb->xc[cells[k]];
+            J[k] = fa[k] * jb->jump;
+        }
+        rc = ig4_ext(J, NULL, n, dj, NULL);
+    }
+    for (int i = 0; i < n && !rc; ++i) {
+#define GEXT(m) (fa[mod_n((m), n)] * ((x[mod_n((m), n)] + (double)floor_div((m), n) * jb->jump) - x[i]))
+        for (int k = 0; k < n; ++k) {
+            r[k] = IG4_A * (GEXT(k + 1) - GEXT(k - 1)) + IG4_B * (GEXT(k + 2) - GEXT(k - 2));
+            for (int s = -1; s <= 1; s += 2)
+                r[k] -= ig4_alpha * (double)floor_div(k + s, n) * dj[mod_n(k + s, n)];
+        }
+        double v[5], y[5];  /* cells i-2 .. i+2 */
+        for (int q = 0; q < 5; ++q) {
+            int m = i - 2 + q, row = mod_n(m, n);
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += jb->ainv[(long)row * n + k] * r[k];
+            y[q] = acc + (double)floor_div(m, n) * dj[row];
+            v[q] = GEXT(m);
+        }
+#undef GEXT
+        double face[2];  /* i - 1/2 (cells i-2 .. i+1), i + 1/2 (cells i-1 .. i+2) */
+        for (int h = 0; h < 2; ++h) {
+            const double *vv = v + h, *gg = y + h;  /* vv[0..3] = cells (i-2+h) .. (i+1+h) */
+            double hl = hermite(vv + 1, gg + 1);
+            double hr = hermite(vv + 2, gg + 2);
+            double left = vv[1] + 0.5 * gg[1] + hl / 12.0;
+            double right = vv[2] - 0.5 * gg[2] + hr / 12.0;
+            face[h] = 0.5 * (left + right);
+        }
+        jb->out[cells[i]] = face[1] - face[0];
+    }
+    free(fa); free(x); free(J); free(dj); free(r);
+    return rc;
+}
+
 static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t, double *m)
 {
     const long N = ncell_of(g);
     double *dx = (double *)malloc(sizeof(double) * 9 * N);
     double *ta = (double *)malloc(sizeof(double) * N);
     double *tb = (double *)malloc(sizeof(double) * N);
+    double *ainv[3] = {NULL, NULL, NULL};
     int rc = (!dx || !ta || !tb) ? -1 : 0;
+    for (int d = 0; d < 3 && !rc; ++d)
+        if (!(ainv[d] = ig4_inverse(g->n[d]))) rc = -1;
     /* Step 1: coordinate derivatives D_d(x_c). */
     for (int d = 0; d < 3 && !rc; ++d)
         for (int c = 0; c < 3 && !rc; ++c) {
-            line_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], NULL, dx + (d * 3 + c) * N, 0, NULL};
-            rc = run_job(jb);
+            dloc_job jb = {g, d, NULL, xyz + c * N, g->off[d][c], dx + (d * 3 + c) * N, ainv[d]};
+            rc = for_lines(g, d, dloc_fn, &jb);
         }
     /* Step 2: hat(d)_c = D_d2[(c1)_d1 * c2] - D_d1[(c1)_d2 * c2]; the product
      * shifts by (c1)_d1 * off[d2][c2] when the d2 index wraps.            */
@@ -555,10 +665,10 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
         int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3 && !rc; ++c) {
             int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-            line_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], NULL, ta, 0, NULL};
-            line_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], NULL, tb, 0, NULL};
-            rc = run_job(ja);
-            if (!rc) rc = run_job(jc);
+            dloc_job ja = {g, d2, dx + (d1 * 3 + c1) * N, xyz + c2 * N, g->off[d2][c2], ta, ainv[d2]};
+            dloc_job jc = {g, d1, dx + (d2 * 3 + c1) * N, xyz + c2 * N, g->off[d1][c2], tb, ainv[d1]};
+            rc = for_lines(g, d2, dloc_fn, &ja);
+            if (!rc) rc = for_lines(g, d1, dloc_fn, &jc);
             if (!rc)
                 for (long idx = 0; idx < N; ++idx) m[REF_M_HAT(d, c) * N + idx] = ta[idx] - tb[idx];
         }
@@ -617,6 +727,7 @@ static int metrics_mig4(const ref_cfg *g, const double *xyz, const double *xyz_t
             m[REF_M_INVJT * N + idx] = -sum;
         }
     free(dx); free(ta); free(tb);
+    for (int d = 0; d < 3; ++d) free(ainv[d]);
     if (rc) return -1;
     return bad ? 1 : 0;
 }
