@@ -346,12 +346,42 @@ static int for_lines(const ref_cfg *g, int d, int (*fn)(void *, const long *), v
     return rc;
 }
 
+/* (x + wraps * off) - org, the position of a periodic image of x relative to
+ * org, with one rounding of the small result. The image x + wraps * off is
+ * not representable in general (x and off of the size of the domain, the
+ * result of the size of a cell): formed in one rounded step it carries an
+ * error of eps |x| that the metrics divide by the spacing. Here the product
+ * and the sum are split into exact value and error pairs (the product error
+ * from a fused multiply-add, the sum error from the two-sum of Knuth), the
+ * leading part minus org is exact when the image lies near org, and the
+ * error terms are added last. In exact arithmetic this is the periodic
+ * extension of the coordinates (Sec. 4.2); only the rounding changes. */
+static double image_rel(double x, int wraps, double off, double org)
+{
+    if (wraps == 0) return x - org;
+    const double p = (double)wraps * off;
+    const double pe = fma((double)wraps, off, -p);
+    const double s = x + p;
+    const double bp = s - x;
+    const double se = (x - (s - bp)) + (p - bp);
+    return (s - org) + (se + pe);
+}
+
 /* Coordinate c of the periodic extension at neighbour m along d of a cell. */
 static double coord_ext(const ref_cfg *g, const double *xyz, const int ijk[3], int d, int m, int c)
 {
     int wraps;
     long nb = neighbour(g, ijk, d, m, &wraps);
     return xyz[c * ncell_of(g) + nb] + (double)wraps * g->off[d][c];
+}
+
+/* Coordinate c of the periodic extension at neighbour m along d of a cell,
+ * measured from org. */
+static double coord_rel(const ref_cfg *g, const double *xyz, const int ijk[3], int d, int m, int c, double org)
+{
+    int wraps;
+    long nb = neighbour(g, ijk, d, m, &wraps);
+    return image_rel(xyz[c * ncell_of(g) + nb], wraps, g->off[d][c], org);
 }
 
 /* Window of a periodic cell field along d (no shift). */
@@ -385,7 +415,8 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
      * coordinate, which vanishes since the central derivatives commute), so
      * every cell evaluates its windows with coordinates measured from its own
      * centre. This only removes cancellation of O(|x| / dx) on grids far from
-     * the origin.
+     * the origin; across the periodic seam the image is placed relative to
+     * the centre with one rounding (image_rel).
      * Step 1: coordinate derivatives D_d(x_c) at cell centres. */
 #pragma omp parallel for schedule(static)
     for (long idx = 0; idx < N; ++idx) {
@@ -394,7 +425,7 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
         unpack(g, idx, ijk);
         for (int d = 0; d < 3; ++d)
             for (int c = 0; c < 3; ++c) {
-                for (int q = -5; q <= 5; ++q) w[q + 5] = coord_ext(g, xyz, ijk, d, q, c) - xyz[c * N + idx];
+                for (int q = -5; q <= 5; ++q) w[q + 5] = coord_rel(g, xyz, ijk, d, q, c, xyz[c * N + idx]);
                 dx[(d * 3 + c) * N + idx] = dcomp(w + 5);
             }
     }
@@ -415,11 +446,11 @@ int ref_metrics(const ref_cfg *g, const double *xyz, const double *xyz_t, double
                 const double org = xyz[c2 * N + idx];
                 for (int q = -5; q <= 5; ++q)
                     w[q + 5] = dx[(d1 * 3 + c1) * N + neighbour(g, ijk, d2, q, NULL)]
-                               * (coord_ext(g, xyz, ijk, d2, q, c2) - org);
+                               * coord_rel(g, xyz, ijk, d2, q, c2, org);
                 double ta = dcomp(w + 5);
                 for (int q = -5; q <= 5; ++q)
                     w[q + 5] = dx[(d2 * 3 + c1) * N + neighbour(g, ijk, d1, q, NULL)]
-                               * (coord_ext(g, xyz, ijk, d1, q, c2) - org);
+                               * coord_rel(g, xyz, ijk, d1, q, c2, org);
                 double tb = dcomp(w + 5);
                 m[REF_M_HAT(d, c) * N + idx] = ta - tb;
             }
@@ -580,8 +611,8 @@ static double *ig4_inverse(int n)
 
 /* D_d of the line F = fac * x (fac NULL: 1) at every cell i, with x measured
  * from cell i: Eq. FP-interp2 applied to G(m) = fac_m ((x_m + w off) - x_i),
- * w the number of periods the index m crossed (the periodic image is formed
- * first, then shifted, as in ref_metrics). G extends with the jump
+ * w the number of periods the index m crossed (the image relative to x_i
+ * rounded once, image_rel, as in ref_metrics). G extends with the jump
  * fac * off per period, so its IG4 derivative (Eq. IG4_grads) is that of
  * ig4_ext, here y = Ainv (r - jump rows) + w dj with dj = IG4 of the jump
  * line; the interface values at i -+ 1/2 follow ig4_faces.               */
@@ -612,20 +643,28 @@ static int dloc_fn(void *ctx, const long *cells)
         }
         rc = ig4_ext(J, NULL, n, dj, NULL);
     }
+    /* The cyclic system is posed on the period of the extended line that
+     * starts at b = i - n/2, so that the target sits mid-period: the values
+     * it couples most strongly are then those of the cells around it, all
+     * measured from x_i (and small), while the cells half a period away enter
+     * through weights of order 0.42^(n/2). The line F(k) = G(b + k) extends
+     * with the rotated jump, whose IG4 derivative is dj rotated by b (the
+     * circulant inverse is unchanged by the rotation). */
     for (int i = 0; i < n && !rc; ++i) {
-#define GEXT(m) (fa[mod_n((m), n)] * ((x[mod_n((m), n)] + (double)floor_div((m), n) * jb->jump) - x[i]))
+        const int b = i - n / 2;
+#define GEXT(m) (fa[mod_n((m), n)] * image_rel(x[mod_n((m), n)], floor_div((m), n), jb->jump, x[i]))
         for (int k = 0; k < n; ++k) {
-            r[k] = IG4_A * (GEXT(k + 1) - GEXT(k - 1)) + IG4_B * (GEXT(k + 2) - GEXT(k - 2));
+            r[k] = IG4_A * (GEXT(b + k + 1) - GEXT(b + k - 1)) + IG4_B * (GEXT(b + k + 2) - GEXT(b + k - 2));
             for (int s = -1; s <= 1; s += 2)
-                r[k] -= ig4_alpha * (double)floor_div(k + s, n) * dj[mod_n(k + s, n)];
+                r[k] -= ig4_alpha * (double)floor_div(k + s, n) * dj[mod_n(b + k + s, n)];
         }
         double v[5], y[5];  /* cells i-2 .. i+2 */
         for (int q = 0; q < 5; ++q) {
-            int m = i - 2 + q, row = mod_n(m, n);
+            int m = i - 2 + q - b, row = mod_n(m, n);  /* position in the rotated period */
             double acc = 0.0;
             for (int k = 0; k < n; ++k) acc += jb->ainv[(long)row * n + k] * r[k];
-            y[q] = acc + (double)floor_div(m, n) * dj[row];
-            v[q] = GEXT(m);
+            y[q] = acc + (double)floor_div(m, n) * dj[mod_n(m + b, n)];
+            v[q] = GEXT(i - 2 + q);
         }
 #undef GEXT
         double face[2];  /* i - 1/2 (cells i-2 .. i+1), i + 1/2 (cells i-1 .. i+2) */
@@ -889,7 +928,17 @@ static int bjob_fn(void *ctx, const long *cells)
             for (int q = 0; q < n; ++q) G[q] = (jb->fac ? jb->fac[cells[q]] : 1.0) * (jb->xc[cells[q]] - o);
             V = G;
         }
-        if (!bnd) {
+        if (!bnd && !jb->faces && jb->org) {
+            /* periodic direction: the window of the extended line around k,
+             * each image measured from the target with one rounding */
+            const double o = jb->org[cells[k]];
+            double w[11];
+            for (int q = -5; q <= 5; ++q) {
+                int b = k + q, r = mod_n(b, n);
+                w[q + 5] = (jb->fac ? jb->fac[cells[r]] : 1.0) * image_rel(jb->xc[cells[r]], floor_div(b, n), jb->jump, o);
+            }
+            jb->out[cells[k]] = dcomp(w + 5);
+        } else if (!bnd) {
             double up = pline_face_at(V, jb->faces ? NULL : J, n, k);
             jb->out[cells[k]] = jb->faces ? up : up - pline_face_at(V, J, n, k - 1);
         } else if (jb->faces) {

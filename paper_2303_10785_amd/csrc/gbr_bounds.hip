@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv_b(BArgs a, BoundRows br)
         for (int c = 0; c < 3; ++c) {
             const double org = coord(a, c, idx);
             a.dx[(d * 3 + c) * a.dm.ncell + idx] = deriv(a, br, ijk, d, [&](const int t[3], int wr) {
-                return (coord(a, c, pack(a.dm, t)) + wr * a.off[d][c]) - org;
+                return image_rel(coord(a, c, pack(a.dm, t)), wr, a.off[d][c], org);
             });
         }
 }
@@ -209,11 +209,11 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics_b(BArgs a, BoundRows br
             const double org = coord(a, c2, idx);
             const double ta = deriv(a, br, ijk, d2, [&](const int t[3], int wr) {
                 const long nb = pack(a.dm, t);
-                return a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d2][c2]) - org);
+                return a.dx[(d1 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d2][c2], org);
             });
             const double tb = deriv(a, br, ijk, d1, [&](const int t[3], int wr) {
                 const long nb = pack(a.dm, t);
-                return a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d1][c2]) - org);
+                return a.dx[(d2 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d1][c2], org);
             });
             hat[d][c] = ta - tb;
         }

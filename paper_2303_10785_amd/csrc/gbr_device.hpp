@@ -23,6 +23,29 @@ __device__ __forceinline__ int wrap_count(int a, int n)
     return (a - r) / n;
 }
 
+// Position of the periodic image x + wr * off relative to org, with one
+// rounding of the small result: the metrics are invariant under a translation
+// (Sec. 4.2), so every window is measured from its target cell, but the image
+// x + wr * off of a cell across the seam is not representable in general and,
+// rounded first, would carry an error of eps |x| that the metrics divide by
+// the spacing. The product and the sum are split into exact value and error
+// pairs (the product error from a fused multiply-add, the sum error from
+// Knuth's two-sum), the leading part minus org is exact when the image lies
+// near org, and the error terms are added last. No contraction may merge
+// these operations.
+__device__ __forceinline__ double image_rel(double x, int wr, double off, double org)
+{
+#pragma clang fp contract(off)
+    if (wr == 0) return x - org;
+    const double w = double(wr);
+    const double p = w * off;
+    const double pe = __builtin_fma(w, off, -p);
+    const double s = x + p;
+    const double bp = s - x;
+    const double se = (x - (s - bp)) + (p - bp);
+    return (s - org) + (se + pe);
+}
+
 // Composite central derivative of Sec. 7: the difference of two interface
 // values of the averaged van Leer states built on E6 gradients and Hermite
 // second derivatives, which collapses to sum_m c_m (v[+m] - v[-m]) with

@@ -100,15 +100,15 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricS
     unpack(a.dm, idx, ijk);
     // Coordinates are measured from the cell's own centre: the metrics are
     // translation invariant and this avoids cancellation of O(|x| / dx).
-    // The periodic image (x + wraps * offset) is formed first, then shifted,
-    // so a window across the seam rounds like one that does not cross it.
+    // Across the periodic seam the image is placed relative to the centre
+    // with one rounding (image_rel).
     for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 3; ++c) {
             const double org = coord(a, c, idx);
             a.dx[(d * 3 + c) * a.dm.ncell + idx] = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d, q, &wr);
-                return (coord(a, c, nb) + wr * a.off[d][c]) - org;
+                return image_rel(coord(a, c, nb), wr, a.off[d][c], org);
             });
         }
 }
@@ -130,12 +130,12 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a, Ig4Metric
             double ta = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d2, q, &wr);
-                return a.dx[(d1 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d2][c2]) - org);
+                return a.dx[(d1 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d2][c2], org);
             });
             double tb = composite<IG4>(st, [&](int q) {
                 int wr;
                 long nb = step_to(a.dm, ijk, d1, q, &wr);
-                return a.dx[(d2 * 3 + c1) * N + nb] * ((coord(a, c2, nb) + wr * a.off[d1][c2]) - org);
+                return a.dx[(d2 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d1][c2], org);
             });
             hat[d][c] = ta - tb;
         }
