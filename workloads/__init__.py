@@ -388,6 +388,33 @@ def random_rough_state(grid, seed=0, amp=0.3, gamma=1.4):
     return conserved(rho, u, v, w, p, gamma, grid["ndim"])
 
 
+def supersonic_rough_state(grid, seed=0, mach=3.0, amp=0.1, gamma=1.4):
+    """Streams that cross each cell face family at up to `mach` times the sound
+    speed, in both directions, with cell-to-cell noise on top.
+
+    u depends on the (j, k) index of its xi line, v on (i, k), w on (i, j), as
+    a cosine of the line index: every xi line carries one sign of u, and lines
+    with |cos| > 1/mach (plus the noise) are supersonic through all of their
+    xi faces. Across the lines both signs occur, so both one-sided flux
+    branches of HLLC (all waves moving right, all moving left) and the star
+    branches near the sign changes are taken along every direction."""
+    rng = np.random.default_rng(SEED_BASE + 250 + seed)
+    shp = grid["xyz"].shape[1:]
+    nk, nj, ni = shp
+    k, j, i = np.meshgrid(np.arange(nk), np.arange(nj), np.arange(ni), indexing="ij")
+    rho = 1.0 + amp * rng.uniform(-1, 1, shp)
+    p = 1.0 / gamma + (amp / gamma) * rng.uniform(-1, 1, shp)
+    c = np.sqrt(gamma * p / rho)
+    # phases chosen so that no line sits exactly on a sign change
+    u = mach * c * np.cos(2 * np.pi * (j + 0.31) / nj + 2 * np.pi * (k + 0.17) / max(nk, 2))
+    v = mach * c * np.cos(2 * np.pi * (i + 0.23) / ni + 2 * np.pi * (k + 0.41) / max(nk, 2))
+    w = mach * c * np.cos(2 * np.pi * (i + 0.37) / ni + 2 * np.pi * (j + 0.11) / nj)
+    u = u + amp * c * rng.uniform(-1, 1, shp)
+    v = v + amp * c * rng.uniform(-1, 1, shp)
+    w = (w + amp * c * rng.uniform(-1, 1, shp)) if grid["ndim"] == 3 else np.zeros(shp)
+    return conserved(rho, u, v, w, p, gamma, grid["ndim"])
+
+
 def vortex_sod(grid, eps=2.0, xc=None, yc=None, gamma=1.4):
     """Sod-type (rho, p) = (1, 1) | (0.125, 0.1) split at x = L/2 (periodic, so
     a second jump sits at the seam), with an isentropic vortex of strength eps
