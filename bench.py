@@ -7,7 +7,16 @@ sweeps with characteristic MP reconstruction, HLLC and alpha-damping
 viscous flux) each followed by an SSP-RK3 stage. Inputs (grid metrics and
 the state) are resident in HBM before timing starts.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+The headline roofline is one RHS evaluation against its algorithmic bytes
+(Q in, interface metrics in, Res out, and the sensor's cell metrics: 440 B
+per cell for 3-D Navier-Stokes in FP64), next to the counter-measured bytes
+and the bandwidth a streaming triad reaches on the same device. Further legs:
+FP32-bulk and MIG4 on the same workload, the bounded spatial jet, the
+deforming 128^3 grid, the batched many-grid workload, the serving loop, and
+the CPU oracle on the host (all threads and one).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+                  [--no-bounded] [--no-serve]
 
 Prints ONE JSON line on stdout (everything else goes to stderr).
 """
@@ -34,10 +43,30 @@ PAPER_CONTEXT = {
               "(FP64, MEG6 + alpha-damping, real jet with sponge/BCs); context, not this workload",
 }
 
-# Algorithmic (compulsory) HBM bytes per cell for each kernel class, 3-D
-# Navier-Stokes, FP64, static grid, Ducros sensor on: every input read once,
-# every output written once.
-ALG_BYTES_PER_CELL = {
+# Algorithmic bytes per cell per RHS evaluation: what any implementation
+# must move between HBM and the chip for one RHS, i.e. Q in, the interface
+# metrics of the three face families in, Res out; the Ducros sensor adds the
+# nine cell metrics it needs and a moving grid the temporal face metrics.
+def alg_bytes_per_cell_rhs(ndim=3, viscous=True, sensor=True, moving=False, fp32_res=False):
+    nvar = ndim + 2
+    per_family = ndim if not viscous else ndim + ndim * ndim  # hatted + unhatted face metrics
+    b = nvar * 8 + ndim * per_family * 8 + nvar * (4 if fp32_res else 8)
+    if sensor:
+        b += ndim * ndim * 8
+    if moving:
+        b += ndim * 8
+    return b
+
+
+ALG_BYTES_PER_CELL_RHS = alg_bytes_per_cell_rhs()  # 440 B: 3-D NS, FP64, static, sensor on
+
+# Bytes per cell each kernel class of this implementation moves when every
+# one of its inputs is read once and every output written once, counting the
+# intermediates this design keeps in HBM (primitives, the 12 cell gradients,
+# theta, Res between sweeps, the stage buffers). These are the
+# implementation's own bytes, reported per kernel beside the measured
+# counter traffic; the headline roofline uses the algorithmic bytes above.
+IMPL_BYTES_PER_CELL = {
     "prims": 40 + 48,                     # Q -> rho, u, v, w, p, T
     "cell_grad": 32 + 72 + 96 + 8,        # u, v, w, T, 9 cell metrics -> 12 gradients, theta
     # the sweeps run zeta, eta, xi: zeta writes Res, eta adds to it, and xi,
@@ -66,10 +95,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a copy-kernel calibration), or
-    None if absent or taken on different kernel sources."""
+def read_traffic():
+    """HBM bytes per launch of each kernel class from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a streaming-kernel
+    calibration), or None if absent or taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic_jet13m.txt")
     if not os.path.exists(path):
         return None
@@ -82,26 +111,81 @@ def read_traffic(kernel):
                 vals[k.strip()] = v.strip()
     if vals.get("source_digest") != source_digest():
         return None
-    key = f"{kernel}_bytes_per_launch"
-    return float(vals[key]) if key in vals else None
+    out = {}
+    for k, v in vals.items():
+        if k.endswith("_bytes_per_launch") and not k.endswith("_alg_bytes_per_launch"):
+            out[k[: -len("_bytes_per_launch")]] = float(v)
+    return out
+
+
+def triad_probe(dev, n=1 << 26, reps=20):
+    """Achievable HBM bandwidth: the library's STREAM-triad probe a = b + s c
+    over three arrays of n doubles (24 n bytes per launch), best of reps
+    launches timed with events on the current stream."""
+    import torch
+
+    from paper_2303_10785_amd import gbr
+
+    a = torch.empty(n, dtype=torch.float64, device=dev)
+    b = torch.rand(n, dtype=torch.float64, device=dev)
+    c = torch.rand(n, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        gbr.gbr_probe_triad(a, b, c, 0.5)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        gbr.gbr_probe_triad(a, b, c, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    ok = bool(torch.equal(a[:4096], b[:4096] + 0.5 * c[:4096]))
+    del a, b, c
+    torch.cuda.empty_cache()
+    gbs = 24.0 * n / best / 1e9
+    log(f"bench: triad probe {gbs:.0f} GB/s ({24 * n / 2**30:.2f} GiB per launch, best of {reps})")
+    return {"GBps": gbs, "bytes_per_launch": 24 * n, "best_ms": best * 1e3, "check": ok}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(grid, Q):
-    """The oracle as it stands, timed for one RHS evaluation on the full
-    workload (its metrics computed beforehand, not timed)."""
+    """The oracle as it stands, timed for one RHS evaluation of the full
+    workload (its metrics computed beforehand, not timed) on every host thread
+    the process may use and on one thread."""
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    oracle.set_num_threads(threads)
     log(f"cpu baseline: oracle metrics on {NI}x{NJ}x{NK} ({threads} threads)")
     m = oracle.metrics(grid, **PARAMS)
-    log("cpu baseline: timing one oracle RHS")
+    ncell = NI * NJ * NK
+    log("cpu baseline: timing one oracle RHS on all threads")
     t0 = time.perf_counter()
     oracle.rhs(grid, m, Q, **PARAMS)
     t = time.perf_counter() - t0
-    ncell = NI * NJ * NK
+    log("cpu baseline: timing one oracle RHS on one thread")
+    oracle.set_num_threads(1)
+    t0 = time.perf_counter()
+    oracle.rhs(grid, m, Q, **PARAMS)
+    t1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    log(f"cpu baseline: {t:.2f} s on {threads} threads, {t1:.2f} s on one")
     return {"value": ncell / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one RHS evaluation of the full {NI}x{NJ}x{NK} jet workload "
-                      f"(NS, Ducros-gated MP, FP64), metrics precomputed; {t:.2f} s"}
+                      f"(NS, Ducros-gated MP, FP64), metrics precomputed; {t:.2f} s on {threads} threads",
+            "single_core": {"value": ncell / t1, "unit": "cell-updates/s", "cores": 1, "seconds": t1},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0))}
 
 
 def fp32_bulk_leg(G64, grid, Q0, args, dev, ncell):
@@ -248,13 +332,11 @@ def moving_leg(args, dev):
     base = torch.from_numpy(mv.base).to(dev)
     mode = torch.from_numpy(mv.mode).to(dev)
     w = 2 * math.pi * mv.omega
-    dt = torch.zeros(1, dtype=torch.float64, device=dev)
     t = torch.zeros(1, dtype=torch.float64, device=dev)  # mesh time, kept on the device
 
     def step():
         G.step(Q, 0.2, gbr.GBR_DT_CFL, xyz=base + torch.sin(w * t) * mode,
-               xyz_t=(w * torch.cos(w * t)) * mode, dt_out=dt)
-        t.add_(dt)
+               xyz_t=(w * torch.cos(w * t)) * mode, t=t)  # the library advances t by dt
 
     for _ in range(args.warmup):
         step()
@@ -375,6 +457,51 @@ def batched_leg(dev):
     return out
 
 
+SERVE_BURST = 30
+SERVE_PACED = 80
+
+
+def serving_leg(dev):
+    """Serving workload (Poisson stream of 2-D 64^2..1024^2 and 3-D
+    64^3..256^3 wavy-grid Euler requests, 20..500 SSP-RK3 steps each, FP64 or
+    FP32-bulk, admitted against 0.8 x the free HBM), bounded in time: the first
+    SERVE_BURST requests of the seeded trace arrive at once to measure the
+    served capacity, then the first SERVE_PACED requests arrive at the
+    trace's own Poisson times rescaled so that the offered load is 0.8 x that
+    capacity. Reports latency and queue-wait percentiles, solves/s and
+    offered against achieved cell-updates/s for the paced run."""
+    import torch
+
+    from paper_2303_10785_amd import serve
+
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    trace = serve.make_trace(SERVE_PACED)
+    ex = serve.GpuExecutor()
+    t0 = time.perf_counter()
+    burst = serve.run(serve.rescale(trace[:SERVE_BURST], 1e9), ex, budget, log=log)
+    cap = burst["achieved_cell_updates_per_s"]
+    log(f"bench serving: burst of {SERVE_BURST} in {time.perf_counter() - t0:.1f} s, capacity {cap:.3e} cell-RHS/s")
+    offered = sum(r.work for r in trace) / max(r.arrival for r in trace)
+    factor = 0.8 * cap / offered
+    t0 = time.perf_counter()
+    paced = serve.run(serve.rescale(trace, factor), ex, budget, log=log)
+    ex.close()
+    log(f"bench serving: paced {SERVE_PACED} requests in {time.perf_counter() - t0:.1f} s, "
+        f"p50/p99 latency {paced['latency_p50_s']:.2f}/{paced['latency_p99_s']:.2f} s")
+    return {"workload": f"Poisson trace (seed 5) of 2-D 64^2..1024^2 / 3-D 64^3..256^3 wavy-grid Euler requests, "
+                        f"20..500 SSP-RK3 steps, FP64 or FP32-bulk, HBM budget 0.8 x free",
+            "budget_bytes": budget,
+            "capacity_burst": dict(burst, requests_in_burst=SERVE_BURST),
+            "paced": dict(paced, rate_per_s=50.0 * factor, offered_over_capacity=0.8),
+            "latency_p50_s": paced["latency_p50_s"], "latency_p99_s": paced["latency_p99_s"],
+            "queue_wait_p50_s": paced["queue_wait_p50_s"], "queue_wait_p99_s": paced["queue_wait_p99_s"],
+            "solves_per_s": paced["solves_per_s"],
+            "offered_cell_updates_per_s": paced["offered_cell_updates_per_s"],
+            "achieved_cell_updates_per_s": paced["achieved_cell_updates_per_s"],
+            "all_states_ok": burst["all_states_ok"] and paced["all_states_ok"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +509,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched many-grid leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-bounded", action="store_true",
                     help="skip the bounded spatial-jet and deforming-grid legs (they launch the same kernels "
                          "at other sizes, so profiles of the periodic workload leave them out)")
@@ -455,20 +583,36 @@ def main():
     breakdown = {}
     for k, (ms, cnt) in kern.items():
         if cnt:
-            breakdown[k] = {"ms_per_launch": ms / cnt, "launches": cnt,
+            breakdown[k] = {"ms_per_launch": ms / cnt, "launches_per_step": cnt / args.steps,
                             "share": ms / ms_total}
-    dom = max((k for k in breakdown if k in ALG_BYTES_PER_CELL),
-              key=lambda k: breakdown[k]["ms_per_launch"] * breakdown[k]["launches"])
-    alg = ALG_BYTES_PER_CELL[dom] * ncell
-    avg_s = breakdown[dom]["ms_per_launch"] * 1e-3
-    achieved = alg / avg_s / 1e9
-    traffic = read_traffic(dom)
+    # headline roofline: one RHS evaluation (gradients and the three sweeps,
+    # with a third of the step's time-step pass) against the algorithmic
+    # bytes per cell-RHS; its duration is the timed step over three
+    traffic = read_traffic()
+    rhs_s = ms_per_step * 1e-3 / 3
+    achieved = ALG_BYTES_PER_CELL_RHS * ncell / rhs_s / 1e9
+    measured = None
+    if traffic is not None and all(k in traffic for k in breakdown if k in IMPL_BYTES_PER_CELL):
+        measured = sum(traffic[k] * b["launches_per_step"] for k, b in breakdown.items()
+                       if k in IMPL_BYTES_PER_CELL) / 3
     for k, b in breakdown.items():
-        if k in ALG_BYTES_PER_CELL:
-            b["alg_GBps"] = ALG_BYTES_PER_CELL[k] * ncell / (b["ms_per_launch"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "alg_bytes_per_launch": alg}
+        if k in IMPL_BYTES_PER_CELL:
+            b["impl_bytes_per_cell"] = IMPL_BYTES_PER_CELL[k]
+            b["impl_GBps"] = IMPL_BYTES_PER_CELL[k] * ncell / (b["ms_per_launch"] * 1e-3) / 1e9
+            b["impl_frac"] = b["impl_GBps"] / HBM_PEAK_GBS
+            if traffic is not None and k in traffic:
+                b["measured_bytes_per_launch"] = traffic[k]
+                b["measured_GBps"] = traffic[k] / (b["ms_per_launch"] * 1e-3) / 1e9
+    triad = triad_probe(dev)
+    roofline = {"bound": "hbm", "kernel": "rhs (cell gradients + zeta, eta, xi sweeps, 1/3 of the time-step pass)",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured,
+                "alg_bytes_per_cell_rhs": ALG_BYTES_PER_CELL_RHS, "alg_bytes_per_launch": ALG_BYTES_PER_CELL_RHS * ncell,
+                "ms_per_launch": rhs_s * 1e3,
+                "measured_bytes_per_cell_rhs": measured / ncell if measured is not None else None,
+                "measured_GBps": measured / rhs_s / 1e9 if measured is not None else None,
+                "achievable": triad["GBps"], "frac_of_achievable": achieved / triad["GBps"],
+                "achievable_probe": "STREAM triad a = b + s c over 3 x 2^26 doubles (gbr_probe_triad)"}
 
     # FP32-bulk on the same workload: step time and the error of one RHS
     # against the FP64 path (which matches the oracle to 1e-12)
@@ -508,6 +652,8 @@ def main():
     del Q
     torch.cuda.empty_cache()
     line["batched"] = None if args.no_batch else batched_leg(dev)
+    torch.cuda.empty_cache()
+    line["serving"] = None if args.no_serve else serving_leg(dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(grid, Q0)
     else:

@@ -206,14 +206,20 @@ gbr_status gbr_cfl(const gbr_grid *g, int n, const double *const *Q, double cfl,
  * t^n from xyz[b], xyz_t[b] (Sec. 4.2: recomputed once per step), then the
  * time step (dt_mode GBR_DT_CFL: cfl_or_dt is the CFL number; GBR_DT_FIXED:
  * cfl_or_dt is dt), then three RHS evaluations and stages. Qn and Res are
- * library-owned. dt_out[b] (device pointer, may be NULL / the array may be
- * NULL) receives the step's dt. Bounded grids advance interior cells only;
- * each stage sets ghost primitives from the boundary types, and at the end
- * of the step the outflow and wall ghost cells of Q receive their states
- * (inflow ghost cells are never written). Asynchronous.                    */
+ * library-owned. dt_out[b] (device pointer to one double, may be NULL / the
+ * array may be NULL) receives the step's dt. t[b] (device pointer to one
+ * double, the grid's time, may be NULL / the array may be NULL) is advanced
+ * by the step's dt on the device (t^{n+1} = t^n + dt, App. B), so a caller
+ * can step a grid without reading dt back; it must not alias dt_out[b]
+ * (GBR_E_ARG). The coordinates of a moving grid are the caller's mesh at
+ * t^n; the library evaluates no mesh motion itself. Bounded grids advance
+ * interior cells only; each stage sets ghost primitives from the boundary
+ * types, and at the end of the step the outflow and wall ghost cells of Q
+ * receive their states (inflow ghost cells are never written).
+ * Asynchronous.                                                            */
 gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *const *xyz,
                     const double *const *xyz_t, double cfl_or_dt, int dt_mode,
-                    double *const *dt_out);
+                    double *const *dt_out, double *const *t);
 
 /* Synchronise g's stream and report flags raised since the last check:
  * GBR_E_STATE (non-physical state) or GBR_E_JACOBIAN (from a gbr_step metric
@@ -331,6 +337,15 @@ gbr_status gbr_batch_query(gbr_batch b, double *t, double *dt, int *tile);
 
 /* Wait for the batch and release it (not the grids). NULL is accepted.     */
 gbr_status gbr_batch_destroy(gbr_batch b);
+
+/* Measurement probe, not part of the solver: the STREAM triad
+ * a[i] = b[i] + s c[i], i < n, enqueued on hip_stream (a hipStream_t or
+ * NULL). a, b, c are device arrays of n doubles, 16-byte aligned, a not
+ * overlapping b or c. Its rate, 24 n bytes over the kernel time, is the
+ * achievable HBM bandwidth the solver's kernels are reported against.
+ * Errors: GBR_E_ARG (n < 0, null or misaligned pointer), GBR_E_DEVICE. */
+gbr_status gbr_probe_triad(double *a, const double *b, const double *c, double s, long n,
+                           void *hip_stream);
 
 /* Message for the last error on g (static text for g == NULL). Valid until
  * the next call on g.                                                       */

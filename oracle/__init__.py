@@ -130,6 +130,18 @@ def lib():
     return _lib
 
 
+def set_num_threads(n):
+    """Number of OpenMP threads the oracle's parallel loops use from now on
+    (the library's OpenMP runtime, loaded with it). Returns the previous
+    maximum."""
+    lib()
+    omp = C.CDLL("libgomp.so.1")
+    omp.omp_get_max_threads.restype = C.c_int
+    prev = int(omp.omp_get_max_threads())
+    omp.omp_set_num_threads(C.c_int(int(n)))
+    return prev
+
+
 def _ptr(a):
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(_P)

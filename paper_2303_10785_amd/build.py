@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["gbr_api.hip", "gbr_metrics.hip", "gbr_rhs.hip", "gbr_batch.hip", "gbr_stencil.hip", "gbr_bounds.hip"]
+SOURCES = ["gbr_api.hip", "gbr_metrics.hip", "gbr_rhs.hip", "gbr_batch.hip", "gbr_stencil.hip", "gbr_bounds.hip",
+           "gbr_probe.hip"]
 ARCH = os.environ.get("GBR_OFFLOAD_ARCH", "gfx950")
 
 

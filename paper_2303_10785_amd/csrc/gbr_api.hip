@@ -338,7 +338,8 @@ gbr_status gbr_cfl(const gbr_grid *g, int n, const double *const *Q, double cfl,
 }
 
 gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *const *xyz,
-                    const double *const *xyz_t, double cfl_or_dt, int dt_mode, double *const *dt_out)
+                    const double *const *xyz_t, double cfl_or_dt, int dt_mode, double *const *dt_out,
+                    double *const *t)
 {
     gbr_status s = batch_ok(g, n);
     if (s != GBR_OK) return s;
@@ -349,6 +350,8 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
     for (int b = 0; b < n; ++b) {
         gbr_grid_s *gg = g[b];
         if (!Q[b]) return fail(gg, GBR_E_ARG, "null state");
+        double *dto = dt_out ? dt_out[b] : nullptr, *tb = t ? t[b] : nullptr;
+        if (dto && dto == tb) return fail(gg, GBR_E_ARG, "time and time-step outputs alias");
         hipError_t e = hipSuccess;
         if (gg->cfg.moving) {
             const double *x = xyz ? xyz[b] : nullptr;
@@ -366,7 +369,7 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
         for (int st = 0; st < 3 && e == hipSuccess; ++st)
             e = gbr::launch_step_stage(gg, st, gg->dt, Q[b], gg->qn, st == 0 && prims_ready);
         if (e == hipSuccess && gg->bounded) e = gbr::launch_bc_state(gg, Q[b]);
-        if (e == hipSuccess && dt_out && dt_out[b]) e = gbr::launch_copy(gg, dt_out[b], gg->dt, 1);
+        if (e == hipSuccess && (dto || tb)) e = gbr::launch_step_time(gg, gg->dt, dto, tb);
         if (e != hipSuccess) return hip_fail(gg, e, "step launch");
     }
     return GBR_OK;

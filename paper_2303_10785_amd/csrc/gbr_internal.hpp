@@ -143,5 +143,7 @@ template <class R>
 hipError_t launch_sponge(gbr_grid_s *g, const double *Q, R *res);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);
 hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n);
+// End of a gbr_step: dt_out = dt and t += dt (either may be null).
+hipError_t launch_step_time(gbr_grid_s *g, const double *dt, double *dt_out, double *t);
 
 }  // namespace gbr

@@ -853,6 +853,16 @@ __global__ void __launch_bounds__(kBlock) k_copy(double *__restrict__ d, const d
     if (e < n) d[e] = s[e];
 }
 
+// The step's time step to the caller and the grid's time advanced by it
+// (t^{n+1} = t^n + dt).
+__global__ void k_step_time(const double *dt, double *dt_out, double *t)
+{
+    if (threadIdx.x != 0) return;
+    const double d = dt[0];
+    if (dt_out) dt_out[0] = d;
+    if (t) t[0] += d;
+}
+
 template <int D, int NDIM, bool VISC, class R, bool IG4, int TAIL>
 void launch_sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode, int tiles_s, int s_tail)
 {
@@ -1307,6 +1317,14 @@ hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n)
     unsigned blocks = unsigned((n + kBlock - 1) / kBlock);
     Timed timed(g, GBR_K_COPY);
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, g->stream, dst, src, n);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_step_time(gbr_grid_s *g, const double *dt, double *dt_out, double *t)
+{
+    Timed timed(g, GBR_K_COPY);
+    hipLaunchKernelGGL(k_step_time, dim3(1), dim3(64), 0, g->stream, dt, dt_out, t);
     return hipGetLastError();
 }
 

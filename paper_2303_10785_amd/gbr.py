@@ -120,7 +120,7 @@ def lib():
     L.gbr_rhs.argtypes = [_PP, C.c_int, _PP, _PP]
     L.gbr_rk_stage.argtypes = [_PP, C.c_int, C.c_int, _PP, _PP, _PP, _PP]
     L.gbr_cfl.argtypes = [_PP, C.c_int, _PP, C.c_double, _PP]
-    L.gbr_step.argtypes = [_PP, C.c_int, _PP, _PP, _PP, C.c_double, C.c_int, _PP]
+    L.gbr_step.argtypes = [_PP, C.c_int, _PP, _PP, _PP, C.c_double, C.c_int, _PP, _PP]
     L.gbr_check_state.argtypes = [_VP]
     L.gbr_metric_ptr.argtypes = [_VP, C.c_int]
     L.gbr_metric_ptr.restype = _VP
@@ -137,6 +137,8 @@ def lib():
     L.gbr_batch_run.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.c_int]
     L.gbr_batch_query.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.gbr_batch_destroy.argtypes = [_VP]
+    L.gbr_probe_triad.argtypes = [_VP, _VP, _VP, C.c_double, C.c_long, _VP]
+    L.gbr_probe_triad.restype = C.c_int
     for nm in ("gbr_grid_create", "gbr_grid_destroy", "gbr_set_stream", "gbr_metrics", "gbr_rhs",
                "gbr_rk_stage", "gbr_cfl", "gbr_step", "gbr_check_state", "gbr_timing_enable",
                "gbr_timing_collect", "gbr_batch_create", "gbr_batch_run", "gbr_batch_query",
@@ -263,11 +265,12 @@ def gbr_cfl(handles, Q, cfl, dt):
     _check(lib().gbr_cfl(_arr(handles), n, _arr(Q), float(cfl), _arr(dt)), handles[0] if n else None)
 
 
-def gbr_step(handles, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None):
+def gbr_step(handles, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None, t=None):
     n = len(handles)
     _check(lib().gbr_step(_arr(handles), n, _arr(Q), _arr(xyz) if xyz is not None else None,
                           _arr(xyz_t) if xyz_t is not None else None, float(cfl_or_dt), int(dt_mode),
-                          _arr(dt_out) if dt_out is not None else None), handles[0] if n else None)
+                          _arr(dt_out) if dt_out is not None else None,
+                          _arr(t) if t is not None else None), handles[0] if n else None)
 
 
 def gbr_check_state(h):
@@ -304,6 +307,15 @@ def gbr_timing_collect(h):
 
 def gbr_last_error(h):
     return lib().gbr_last_error(h).decode()
+
+
+def gbr_probe_triad(a, b, c, s, stream=None):
+    """a = b + s c over three device tensors of equal length (measurement probe)."""
+    n = a.numel()
+    if b.numel() != n or c.numel() != n:
+        raise ValueError("triad operands differ in length")
+    st = _stream() if stream is None else stream
+    _check(lib().gbr_probe_triad(_ptr(a), _ptr(b), _ptr(c), float(s), n, C.c_void_p(st)))
 
 
 def gbr_batch_create(handles, Q, tile=GBR_TILE_AUTO):
@@ -385,9 +397,11 @@ class Grid:
     def cfl(self, Q, cfl, dt):
         gbr_cfl([self.h], [Q], cfl, [dt])
 
-    def step(self, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None):
+    def step(self, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None, t=None):
+        """t: device tensor of one double, advanced by the step's dt."""
         gbr_step([self.h], [Q], cfl_or_dt, dt_mode, [xyz] if xyz is not None else None,
-                 [xyz_t] if xyz_t is not None else None, [dt_out] if dt_out is not None else None)
+                 [xyz_t] if xyz_t is not None else None, [dt_out] if dt_out is not None else None,
+                 [t] if t is not None else None)
 
     def diagnostics(self, Q, fields=None, integrals=None):
         """fields: device tensor [5][...] or None; integrals: device tensor of

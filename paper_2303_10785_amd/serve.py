@@ -6,15 +6,18 @@ stream; the server
 
 * admits them first-in first-out while their device bytes (``gbr_grid_bytes``
   plus the state and the transient coordinates) fit an HBM budget,
-* advances every admitted request tick by tick: the 2-D requests of one
-  precision form one continuous batch (``gbr_batch``, rebuilt whenever a
-  request joins or leaves), 3-D requests step through ``gbr_step``; within a
-  tick each group advances by the smallest remaining step count of its
-  members (capped), so no request overshoots,
+* runs every admitted request in a group with a HIP stream of its own: the
+  2-D requests of one precision form one continuous batch (``gbr_batch``),
+  each 3-D request steps through ``gbr_step``. Groups advance independently
+  and overlap on the device: whenever a group's last launch has completed
+  (polled through an event, never by synchronising the device), its finished
+  members retire and it is relaunched with its current members for the
+  smallest remaining step count of them (capped), so no request overshoots
+  and a 2-D request that arrived meanwhile joins its batch at that boundary,
 * retires finished requests, releases their bytes and records latency.
 
-The scheduling logic (``Scheduler``) is plain Python and is tested on the
-CPU with a simulated executor; ``GpuExecutor`` drives the C ABI.
+The scheduling logic (``Scheduler``, ``run``) is plain Python and is tested
+on the CPU with a simulated executor; ``GpuExecutor`` drives the C ABI.
 """
 from __future__ import annotations
 
@@ -127,21 +130,25 @@ class Scheduler:
             out.append(r)
         return out
 
-    def plan(self):
-        """{group: steps} for the next tick: each group advances by the
-        smallest remaining count of its members, at most tick_steps."""
+    def plan(self, busy=()):
+        """{group: (steps, rids)} for every group with active members that is
+        not in ``busy``: the members advance together by the smallest
+        remaining count among them, at most tick_steps."""
         groups = {}
         for r in self.active.values():
             g = r.group
-            groups[g] = min(groups.get(g, self.tick_steps), r.remaining)
+            if g in busy:
+                continue
+            k, rids = groups.get(g, (self.tick_steps, []))
+            groups[g] = (min(k, r.remaining), rids + [r.rid])
         return groups
 
-    def advanced(self, group, k, now):
-        """Record that ``group`` advanced k steps; returns the requests that finished."""
+    def advanced(self, rids, k, now):
+        """Record that the requests ``rids`` advanced k steps; returns the
+        requests that finished."""
         done = []
-        for r in list(self.active.values()):
-            if r.group != group:
-                continue
+        for rid in rids:
+            r = self.active[rid]
             r.remaining -= k
             if r.remaining < 0:
                 raise RuntimeError(f"request {r.rid} overshot")
@@ -155,38 +162,49 @@ class Scheduler:
 
 
 def run(trace, executor, budget_bytes, tick_steps=TICK_STEPS, clock=time.perf_counter, sleep=time.sleep,
-        log=None, log_every=20.0):
+        log=None, log_every=20.0, poll_s=2e-4):
     """Serve ``trace`` in real time (arrival times relative to the start) and
     drain it. Returns a summary dict. ``log`` (a callable taking a string)
-    receives a progress line every ``log_every`` seconds."""
+    receives a progress line every ``log_every`` seconds.
+
+    The executor enqueues a group's steps without waiting (``launch``) and
+    reports whether they have completed (``done``); the loop admits arrivals,
+    retires finished requests and relaunches idle groups as soon as each of
+    these becomes possible, and sleeps ``poll_s`` when nothing changed."""
     sched = Scheduler(budget_bytes, executor.bytes_of, tick_steps)
     pending = sorted(trace, key=lambda r: r.arrival)
     t0 = clock()
-    ticks = 0
+    launches = 0
+    inflight = {}  # group -> (steps, rids) of its launch in flight
     last_log = 0.0
-    while pending or sched.queue or sched.active:
+    while pending or sched.queue or sched.active or inflight:
         now = clock() - t0
         if log is not None and now - last_log >= log_every:
             last_log = now
             log(f"[serve] t={now:.1f}s done={len(sched.finished)}/{len(trace)} active={len(sched.active)} "
                 f"queued={len(sched.queue)} pending={len(pending)} used={sched.used / 2**30:.1f}GiB")
+        progressed = False
+        for g in list(inflight):
+            if executor.done(g):
+                k, rids = inflight.pop(g)
+                for r in sched.advanced(rids, k, clock() - t0):
+                    r.state_ok = executor.retire(r)
+                progressed = True
         while pending and pending[0].arrival <= now:
             sched.arrive(pending.pop(0))
-        for r in sched.admit(now):
+        for r in sched.admit(clock() - t0):
             executor.admit(r)
-        if not sched.active:
-            if pending:
-                sleep(max(0.0, min(pending[0].arrival - (clock() - t0), 0.05)))
-            continue
-        plan = sched.plan()
-        for g, k in plan.items():
-            executor.advance(g, k)
-        executor.sync()
-        ticks += 1
-        now = clock() - t0
-        for g, k in plan.items():
-            for r in sched.advanced(g, k, now):
-                r.state_ok = executor.retire(r)
+            progressed = True
+        for g, (k, rids) in sched.plan(busy=inflight).items():
+            executor.launch(g, rids, k)
+            inflight[g] = (k, rids)
+            launches += 1
+            progressed = True
+        if not progressed:
+            wait = poll_s
+            if not inflight and pending:
+                wait = max(poll_s, min(pending[0].arrival - (clock() - t0), 0.05))
+            sleep(wait)
     makespan = clock() - t0
     fin = sched.finished
     lat = [r.done - r.arrival for r in fin]
@@ -195,7 +213,7 @@ def run(trace, executor, budget_bytes, tick_steps=TICK_STEPS, clock=time.perf_co
     work = sum(r.work for r in fin)
     return {
         "requests": len(fin),
-        "ticks": ticks,
+        "launches": launches,
         "makespan_s": makespan,
         "trace_span_s": span,
         "latency_p50_s": percentile(lat, 50),
@@ -283,7 +301,10 @@ def request_inputs(req, dev, L=10.0):
 
 
 class GpuExecutor:
-    """Runs admitted requests through the C ABI on the current device."""
+    """Runs admitted requests through the C ABI on the current device. Each
+    2-D batch group has a stream of its own, and so does each active 3-D
+    request (taken from a pool that grows on demand); a group's launch ends
+    with an event on its stream, which ``done`` polls."""
 
     def __init__(self, dev=None, tile=None, keep_results=False):
         import torch
@@ -293,8 +314,12 @@ class GpuExecutor:
         self.dev = dev or torch.device("cuda", torch.cuda.current_device())
         self.tile = tile or {"fp64": gbr.GBR_TILE_16X16, "fp32_bulk": gbr.GBR_TILE_16X16}
         self.keep = keep_results
-        self.live = {}      # rid -> (Grid, Q)
-        self.batches = {}   # group -> (Batch, [rid...])
+        self.setup = torch.cuda.Stream(device=self.dev)  # inputs and metrics of new requests
+        self.free_streams = []
+        self.streams = {}   # group -> stream
+        self.live = {}      # rid -> (Grid, Q, req)
+        self.batches = {}   # 2-D group -> (Batch, rids)
+        self.events = {}    # group -> event of its last launch
         self.results = {}   # rid -> final state (host), if keep_results
 
     def bytes_of(self, req):
@@ -302,46 +327,66 @@ class GpuExecutor:
                                    [[1, 0, 0], [0, 1, 0], [0, 0, 1]], precision=req.precision)
         return self.gbr.gbr_grid_bytes(cfg) + (req.nvar + 3) * req.ncell * 8
 
+    def _stream_of(self, group):
+        if group not in self.streams:
+            self.streams[group] = self.free_streams.pop() if self.free_streams else \
+                self.torch.cuda.Stream(device=self.dev)
+        return self.streams[group]
+
     def admit(self, req):
-        grid, xyz, Q = request_inputs(req, self.dev)
-        h = self.gbr.Grid(grid, precision=req.precision, viscous=False, limiter="mp")
-        h.metrics(xyz)
-        del xyz
+        """Inputs and metrics on the setup stream (gbr_metrics waits for that
+        stream only), then the grid is rebound to its group's stream."""
+        torch = self.torch
+        with torch.cuda.stream(self.setup):
+            grid, xyz, Q = request_inputs(req, self.dev)
+            h = self.gbr.Grid(grid, precision=req.precision, viscous=False, limiter="mp")
+            h.metrics(xyz)
+            del xyz
+        lane = self._stream_of(req.group)
+        self.gbr.gbr_set_stream(h.h, lane.cuda_stream)
         self.live[req.rid] = (h, Q, req)
-        if req.ndim == 2:
-            self._drop_batch(req.group)
+
+    def launch(self, group, rids, k):
+        torch, gbr = self.torch, self.gbr
+        lane = self._stream_of(group)
+        if group[0] == "3d":
+            h, Q, _ = self.live[group[1]]
+            for _ in range(k):
+                h.step(Q, CFL_3D, gbr.GBR_DT_CFL)
+        else:
+            rids = sorted(rids)
+            if group not in self.batches or self.batches[group][1] != rids:
+                self._drop_batch(group)
+                b = gbr.Batch([self.live[r][0] for r in rids], [self.live[r][1] for r in rids],
+                              tile=self.tile[group[1]])
+                self.batches[group] = (b, rids)
+            self.batches[group][0].run(k, CFL_2D, gbr.GBR_DT_CFL, graph=True)
+        ev = torch.cuda.Event()
+        ev.record(lane)
+        self.events[group] = ev
+
+    def done(self, group):
+        ev = self.events.get(group)
+        return ev is None or ev.query()
 
     def _drop_batch(self, group):
         if group in self.batches:
             self.batches[group][0].close()
             del self.batches[group]
 
-    def advance(self, group, k):
-        if group[0] == "3d":
-            h, Q, _ = self.live[group[1]]
-            for _ in range(k):
-                h.step(Q, CFL_3D, self.gbr.GBR_DT_CFL)
-            return
-        if group not in self.batches:
-            members = [rid for rid, (_, _, r) in self.live.items() if r.group == group]
-            members.sort()
-            b = self.gbr.Batch([self.live[r][0] for r in members], [self.live[r][1] for r in members],
-                               tile=self.tile[group[1]])
-            self.batches[group] = (b, members)
-        self.batches[group][0].run(k, CFL_2D, self.gbr.GBR_DT_CFL, graph=True)
-
-    def sync(self):
-        self.torch.cuda.synchronize()
-
     def retire(self, req):
-        if req.ndim == 2:
-            self._drop_batch(req.group)
         h, Q, _ = self.live.pop(req.rid)
-        ok = h.check_state() == self.gbr.GBR_OK
+        ok = h.check_state() == self.gbr.GBR_OK  # waits for the group's stream (idle here)
         if self.keep:
-            self.results[req.rid] = Q.cpu().numpy()
+            with self.torch.cuda.stream(self._stream_of(req.group)):
+                self.results[req.rid] = Q.cpu().numpy()
+        if req.ndim == 2 and req.group in self.batches and req.rid in self.batches[req.group][1]:
+            self._drop_batch(req.group)
         h.close()
         del Q
+        if req.ndim == 3:
+            self.events.pop(req.group, None)
+            self.free_streams.append(self.streams.pop(req.group))
         return ok
 
     def close(self):
@@ -349,6 +394,7 @@ class GpuExecutor:
             self._drop_batch(g)
         for rid in list(self.live):
             self.live.pop(rid)[0].close()
+        self.torch.cuda.synchronize()
 
 
 def main(argv=None):

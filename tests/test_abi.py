@@ -73,7 +73,7 @@ def test_null_arguments_rejected_without_device_work():
     # empty batches are no-ops
     assert L.gbr_rhs(None, 0, None, None) == gbr.GBR_OK
     assert L.gbr_metrics(None, 0, None, None) == gbr.GBR_OK
-    assert L.gbr_step(None, 0, None, None, None, 0.1, 0, None) == gbr.GBR_OK
+    assert L.gbr_step(None, 0, None, None, None, 0.1, 0, None, None) == gbr.GBR_OK
     assert L.gbr_rhs(None, -1, None, None) == gbr.GBR_E_ARG
     assert L.gbr_check_state(None) == gbr.GBR_E_ARG
     assert L.gbr_last_error(None) == b"null grid handle"

@@ -233,6 +233,34 @@ def test_rk_stage_and_cfl_entry_points(gbr):
     h.close()
 
 
+def test_step_advances_time_per_grid(gbr):
+    """gbr_step adds each step's dt to the caller's per-grid device time
+    (App. B: t^{n+1} = t^n + dt), in CFL and fixed-dt modes, for several
+    grids in one call; the time and dt outputs may not alias."""
+    gs = [GRIDS["random3d_21x13x9"](), GRIDS["wavy2d_37x23_rand"]()]
+    hs, Qs, ts, dts = [], [], [], []
+    for q, g in enumerate(gs):
+        h = gbr.Grid(g, limiter="mp")
+        h.metrics(dev(g["xyz"]))
+        hs.append(h)
+        Qs.append(dev(W.random_smooth_state(g, seed=40 + q)))
+        ts.append(torch.full((1,), 0.25 * (q + 1), dtype=torch.float64, device="cuda"))
+        dts.append(torch.zeros(1, dtype=torch.float64, device="cuda"))
+    expect = [0.25, 0.5]
+    for s in range(4):
+        mode, val = (gbr.GBR_DT_CFL, 0.3) if s % 2 == 0 else (gbr.GBR_DT_FIXED, 1e-3)
+        gbr.gbr_step([h.h for h in hs], Qs, val, mode, dt_out=dts, t=ts)
+        torch.cuda.synchronize()
+        for q in range(2):
+            expect[q] += dts[q].item()
+            assert ts[q].item() == expect[q], (s, q, ts[q].item(), expect[q])
+    with pytest.raises(gbr.GbrError) as ei:
+        hs[0].step(Qs[0], 0.3, gbr.GBR_DT_CFL, dt_out=ts[0], t=ts[0])
+    assert ei.value.status == gbr.GBR_E_ARG
+    for h in hs:
+        h.close()
+
+
 def test_nonphysical_state_is_reported(gbr):
     g = GRIDS["random3d_21x13x9"]()
     Q = W.random_smooth_state(g, seed=13)

@@ -21,7 +21,9 @@ class Clock:
 
 
 class FakeExecutor:
-    """Charges a fixed time per cell-step and counts the steps each request gets."""
+    """Each group runs on a lane of its own (groups overlap fully); a launch
+    of k steps finishes after a fixed time per cell-step of its members.
+    Counts the steps each request gets."""
 
     def __init__(self, clock, sec_per_cell_step=1e-9, bytes_per_cell=100):
         self.clock = clock
@@ -31,6 +33,9 @@ class FakeExecutor:
         self.steps = {}
         self.admitted = []
         self.max_live_bytes = 0
+        self.finish = {}
+        self.launch_log = []
+        self.max_concurrent = 0
 
     def bytes_of(self, r):
         return self.bpc * r.ncell
@@ -41,18 +46,22 @@ class FakeExecutor:
         self.admitted.append(r.rid)
         self.max_live_bytes = max(self.max_live_bytes, sum(self.bytes_of(x) for x in self.live.values()))
 
-    def advance(self, group, k):
-        members = [r for r in self.live.values() if r.group == group]
-        assert members
-        for r in members:
-            self.steps[r.rid] += k
-            self.clock.t += self.cost * r.ncell * k
+    def launch(self, group, rids, k):
+        assert self.done(group), "a group is relaunched only when idle"
+        assert rids and all(self.live[rid].group == group for rid in rids)
+        for rid in rids:
+            self.steps[rid] += k
+        self.finish[group] = self.clock.t + self.cost * k * sum(self.live[rid].ncell for rid in rids)
+        self.launch_log.append((self.clock.t, group, tuple(sorted(rids)), k))
+        busy = sum(1 for f in self.finish.values() if f > self.clock.t)
+        self.max_concurrent = max(self.max_concurrent, busy)
 
-    def sync(self):
-        pass
+    def done(self, group):
+        return self.clock.t >= self.finish.get(group, 0.0)
 
     def retire(self, r):
         assert self.steps[r.rid] == r.steps
+        assert self.done(r.group)
         del self.live[r.rid]
         return True
 
@@ -135,7 +144,30 @@ def test_plan_takes_smallest_remaining_per_group():
     for r in reqs:
         s.arrive(r)
     s.admit(0.0)
-    assert s.plan() == {("2d", "fp64"): 12, ("2d", "fp32_bulk"): 25, ("3d", 3): 5}
-    done = s.advanced(("2d", "fp64"), 12, 1.0)
+    assert s.plan() == {("2d", "fp64"): (12, [0, 1]), ("2d", "fp32_bulk"): (25, [2]), ("3d", 3): (5, [3])}
+    assert s.plan(busy={("2d", "fp64"): None}) == {("2d", "fp32_bulk"): (25, [2]), ("3d", 3): (5, [3])}
+    done = s.advanced([0, 1], 12, 1.0)
     assert [r.rid for r in done] == [1]
-    assert s.plan()[("2d", "fp64")] == 25
+    assert s.plan()[("2d", "fp64")] == (25, [0])
+
+
+def test_groups_overlap_and_late_arrivals_join_at_the_next_launch():
+    """A long 3-D request does not hold up 2-D work: groups run
+    concurrently. A 2-D request arriving while its batch is in flight joins
+    at the batch's next launch, and the in-flight launch does not count
+    steps for it."""
+    clock = Clock()
+    ex = FakeExecutor(clock, sec_per_cell_step=1e-6, bytes_per_cell=1)
+    slow3d = serve.Request(0, 0.0, 3, 20, 50, "fp64", "column", 0)     # 8000 cells x 50 steps
+    a = serve.Request(1, 0.0, 2, 30, 40, "fp64", "vortex", 1)          # 9 ms per 10-step launch
+    b = serve.Request(2, 0.005, 2, 30, 20, "fp64", "sod", 2)
+    out = serve.run([slow3d, a, b], ex, 10 ** 9, tick_steps=10, clock=clock, sleep=clock.sleep)
+    assert out["requests"] == 3 and all(ex.steps[r.rid] == r.steps for r in (slow3d, a, b))
+    assert ex.max_concurrent >= 2
+    # the 2-D requests finish long before the 3-D one
+    assert a.done < slow3d.done and b.done < slow3d.done
+    # b was admitted during a's first launch and first ran with it afterwards
+    first_a = [x for x in ex.launch_log if x[1] == ("2d", "fp64")][0]
+    assert first_a[2] == (1,)
+    joint = [x for x in ex.launch_log if x[2] == (1, 2)]
+    assert joint and joint[0][0] >= b.admitted
