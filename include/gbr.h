@@ -226,6 +226,23 @@ gbr_status gbr_step(const gbr_grid *g, int n, double *const *Q, const double *co
  * update). Clears the flags.                                                */
 gbr_status gbr_check_state(gbr_grid g);
 
+/* gbr_cfl for callers that cannot allocate device memory (code under HIP
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same time step, bitwise, with the per-block partial minima kept in a static
+ * device array of the library (1 MiB per device, reserved until the process
+ * ends; 32 slices of 4096 doubles, slice b for grid b of the call) instead of
+ * the grid's own buffer. Calls no hipMalloc, hipFree or allocating routine
+ * (the device address of the array is looked up once per device on first
+ * use) and records no timing events. At most 32 grids per call (GBR_E_ARG
+ * beyond, with a message in gbr_last_error(g[0])); other errors as gbr_cfl.
+ * Every call on a device shares that device's array: calls whose work
+ * overlaps on one device (different streams, or host threads) race and must
+ * be ordered by the caller; grids of one call on different streams do not
+ * race with each other. The array keeps the last call's partials; each
+ * launch writes every slot it reads, so nothing needs clearing.            */
+gbr_status gbr_cfl_noalloc(const gbr_grid *g, int n, const double *const *Q, double cfl,
+                           double *const *dt);
+
 /* Diagnostics from the cell gradients the scheme shares (Sec. 3 names
  * vorticity, enstrophy, density-gradient magnitude and the Q-criterion as
  * uses of them; Eq. KE-Ens defines the kinetic-energy and enstrophy

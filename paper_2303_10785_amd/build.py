@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["gbr_api.hip", "gbr_metrics.hip", "gbr_rhs.hip", "gbr_batch.hip", "gbr_stencil.hip", "gbr_bounds.hip",
-           "gbr_probe.hip"]
+           "gbr_probe.hip", "gbr_noalloc.hip"]
 ARCH = os.environ.get("GBR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -127,6 +127,9 @@ hipError_t launch_diagnostics(gbr_grid_s *g, const double *Q, double *fields, do
 hipError_t launch_step_stage(gbr_grid_s *g, int stage, const double *dt, double *Q, double *S,
                              bool prims_ready = false);
 hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt);
+// launch_cfl with the per-block minima in `partial` (kReducePartials doubles)
+// and no timing events.
+hipError_t launch_cfl_into(gbr_grid_s *g, const double *Q, double cfl, double *dt, double *partial);
 // launch_cfl plus the primitives of Q for the first stage of gbr_step.
 hipError_t launch_cfl_prims(gbr_grid_s *g, const double *Q, double cfl, double *dt);
 // Non-periodic boundaries (gbr_bounds.hip): App. C metrics of a static grid

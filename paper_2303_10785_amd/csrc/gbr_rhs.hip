@@ -1246,31 +1246,36 @@ hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const dou
     return rk_typed<double>(g, stage, dt, Qn, Q, static_cast<const double *>(res));
 }
 
-hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
+hipError_t launch_cfl_into(gbr_grid_s *g, const double *Q, double cfl, double *dt, double *partial)
 {
     const Dims dm = dims_of(g);
     const Phys ph = phys_of(g);
     long want = (g->ncell + kBlock - 1) / kBlock;
     int blocks = int(want < kReducePartials ? want : kReducePartials);
     const bool visc = g->cfg.viscous != 0;
-    Timed timed(g, GBR_K_CFL);
     if (g->cfg.ndim == 3) {
         if (visc)
             hipLaunchKernelGGL((k_cfl_partial<3, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->cfg.moving, g->partial);
+                               g->metrics, g->cfg.moving, partial);
         else
             hipLaunchKernelGGL((k_cfl_partial<3, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->cfg.moving, g->partial);
+                               g->metrics, g->cfg.moving, partial);
     } else {
         if (visc)
             hipLaunchKernelGGL((k_cfl_partial<2, true>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->cfg.moving, g->partial);
+                               g->metrics, g->cfg.moving, partial);
         else
             hipLaunchKernelGGL((k_cfl_partial<2, false>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, ph, Q,
-                               g->metrics, g->cfg.moving, g->partial);
+                               g->metrics, g->cfg.moving, partial);
     }
-    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, g->partial, blocks, cfl, dt);
+    hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(1024), 0, g->stream, partial, blocks, cfl, dt);
     return hipGetLastError();
+}
+
+hipError_t launch_cfl(gbr_grid_s *g, const double *Q, double cfl, double *dt)
+{
+    Timed timed(g, GBR_K_CFL);
+    return launch_cfl_into(g, Q, cfl, dt, g->partial);
 }
 
 namespace {

@@ -137,6 +137,8 @@ def lib():
     L.gbr_batch_run.argtypes = [_VP, C.c_int, C.c_double, C.c_int, C.c_int]
     L.gbr_batch_query.argtypes = [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_int)]
     L.gbr_batch_destroy.argtypes = [_VP]
+    L.gbr_cfl_noalloc.argtypes = [_PP, C.c_int, _PP, C.c_double, _PP]
+    L.gbr_cfl_noalloc.restype = C.c_int
     L.gbr_probe_triad.argtypes = [_VP, _VP, _VP, C.c_double, C.c_long, _VP]
     L.gbr_probe_triad.restype = C.c_int
     for nm in ("gbr_grid_create", "gbr_grid_destroy", "gbr_set_stream", "gbr_metrics", "gbr_rhs",
@@ -263,6 +265,11 @@ def gbr_rk_stage(handles, stage, dt, Qn, Q, res):
 def gbr_cfl(handles, Q, cfl, dt):
     n = len(handles)
     _check(lib().gbr_cfl(_arr(handles), n, _arr(Q), float(cfl), _arr(dt)), handles[0] if n else None)
+
+
+def gbr_cfl_noalloc(handles, Q, cfl, dt):
+    n = len(handles)
+    _check(lib().gbr_cfl_noalloc(_arr(handles), n, _arr(Q), float(cfl), _arr(dt)), handles[0] if n else None)
 
 
 def gbr_step(handles, Q, cfl_or_dt, dt_mode=GBR_DT_CFL, xyz=None, xyz_t=None, dt_out=None, t=None):
