@@ -32,11 +32,11 @@ __device__ __forceinline__ int wrap_count(int a, int n)
 // pairs (the product error from a fused multiply-add, the sum error from
 // Knuth's two-sum), the leading part minus org is exact when the image lies
 // near org, and the error terms are added last. No contraction may merge
-// these operations.
+// these operations. With wr = 0 every error term is zero and the result is
+// x - org exactly, so the function serves whole windows without a branch.
 __device__ __forceinline__ double image_rel(double x, int wr, double off, double org)
 {
 #pragma clang fp contract(off)
-    if (wr == 0) return x - org;
     const double w = double(wr);
     const double p = w * off;
     const double pe = __builtin_fma(w, off, -p);

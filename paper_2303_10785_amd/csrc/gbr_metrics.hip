@@ -91,6 +91,27 @@ __device__ __forceinline__ double interface(const Ig4MetricStencil &s, F f)
     return face_interp(v + 4);
 }
 
+// Windows of the composite derivative: half-width along the line.
+template <bool IG4>
+constexpr int window_half() { return IG4 ? kIg4DHalf : 5; }
+
+// Whether the window of cell ijk along d, or of another cell of the same
+// wavefront, reaches across the periodic seam (then neighbours enter as
+// periodic images); away from it a neighbour at offset q is the cell q
+// strides along d. Decided per wavefront, so both window forms never run
+// under one mask; image_rel gives the plain difference for cells whose
+// window does not wrap.
+template <bool IG4>
+__device__ __forceinline__ bool near_seam(const Dims &dm, const int ijk[3], int d)
+{
+    return __any(ijk[d] < window_half<IG4>() || ijk[d] >= dm.n[d] - window_half<IG4>());
+}
+
+__device__ __forceinline__ long stride_of(const Dims &dm, int d)
+{
+    return d == 0 ? 1 : (d == 1 ? (long)dm.n[0] : (long)dm.n[0] * dm.n[1]);
+}
+
 template <bool IG4>
 __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricStencil st)
 {
@@ -102,15 +123,20 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricS
     // translation invariant and this avoids cancellation of O(|x| / dx).
     // Across the periodic seam the image is placed relative to the centre
     // with one rounding (image_rel).
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < 3; ++d) {
+        const bool seam = near_seam<IG4>(a.dm, ijk, d);
+        const long sd = stride_of(a.dm, d);
         for (int c = 0; c < 3; ++c) {
             const double org = coord(a, c, idx);
-            a.dx[(d * 3 + c) * a.dm.ncell + idx] = composite<IG4>(st, [&](int q) {
-                int wr;
-                long nb = step_to(a.dm, ijk, d, q, &wr);
-                return image_rel(coord(a, c, nb), wr, a.off[d][c], org);
-            });
+            a.dx[(d * 3 + c) * a.dm.ncell + idx] =
+                seam ? composite<IG4>(st, [&](int q) {
+                    int wr;
+                    long nb = step_to(a.dm, ijk, d, q, &wr);
+                    return image_rel(coord(a, c, nb), wr, a.off[d][c], org);
+                })
+                     : composite<IG4>(st, [&](int q) { return coord(a, c, idx + q * sd) - org; });
         }
+    }
 }
 
 template <bool IG4>
@@ -122,22 +148,27 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a, Ig4Metric
     int ijk[3];
     unpack(a.dm, idx, ijk);
     double hat[3][3];
+    // D_e of (c1)_f * c2 along direction e at this cell, c2 measured from org
+    auto dprod = [&](int e, int f, int c1, int c2, double org) {
+        const double *fac = a.dx + (f * 3 + c1) * N;
+        if (near_seam<IG4>(a.dm, ijk, e))
+            return composite<IG4>(st, [&](int q) {
+                int wr;
+                long nb = step_to(a.dm, ijk, e, q, &wr);
+                return fac[nb] * image_rel(coord(a, c2, nb), wr, a.off[e][c2], org);
+            });
+        const long se = stride_of(a.dm, e);
+        return composite<IG4>(st, [&](int q) {
+            const long nb = idx + q * se;
+            return fac[nb] * (coord(a, c2, nb) - org);
+        });
+    };
     for (int d = 0; d < 3; ++d) {
         const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
         for (int c = 0; c < 3; ++c) {
             const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
             const double org = coord(a, c2, idx);
-            double ta = composite<IG4>(st, [&](int q) {
-                int wr;
-                long nb = step_to(a.dm, ijk, d2, q, &wr);
-                return a.dx[(d1 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d2][c2], org);
-            });
-            double tb = composite<IG4>(st, [&](int q) {
-                int wr;
-                long nb = step_to(a.dm, ijk, d1, q, &wr);
-                return a.dx[(d2 * 3 + c1) * N + nb] * image_rel(coord(a, c2, nb), wr, a.off[d1][c2], org);
-            });
-            hat[d][c] = ta - tb;
+            hat[d][c] = dprod(d2, d1, c1, c2, org) - dprod(d1, d2, c1, c2, org);
         }
     }
     double x[3][3];
