@@ -91,7 +91,15 @@ struct Ig4MetricStencil {
     double d[kIg4DHalf + 1];     // D f_i = sum_{j = 1..kIg4DHalf} d[j] (f_{i+j} - f_{i-j})
     double e[2 * kIg4Half + 4];  // I_{i+1/2} = sum_{m = -(H+1)..H+2} e[m + H + 1] f_{i+m}, H = kIg4Half
 };
+// Constants of the IG4 gradients as two first-order recurrences (k_ig4_rec):
+// q and K of the factorised left-hand side, the right-hand-side weights a and
+// b, and the powers pw[j] = (-q)^j.
+struct Ig4Rec {
+    double q, K, a, b;
+    double pw[20];
+};
 const Ig4Stencil &ig4_stencil();
+const Ig4Rec &ig4_rec();
 const Ig4MetricStencil &ig4_metric_stencil();
 
 Dims dims_of(const gbr_grid_s *g);

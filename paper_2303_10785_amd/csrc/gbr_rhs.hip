@@ -37,9 +37,6 @@ namespace gbr {
 namespace {
 
 constexpr int kBlock = 256;
-#ifndef GBR_IG4_UNROLL
-#define GBR_IG4_UNROLL 4
-#endif
 #ifndef GBR_TS_CROSS
 #define GBR_TS_CROSS 16
 #endif
@@ -160,44 +157,55 @@ __device__ __forceinline__ R ducros_theta(const R gd[3][4], const R mt[3][3])
     return d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
 }
 
-// MIG4 gradients (Eq. IG4_grads) along direction D of the six primitives
-// with the explicit wide stencil that equals the implicit scheme
-// (gbr_stencil.hip): f'_i = sum_j w_j (f_{i+j} - f_{i-j}), periodic. A
-// workgroup stages a segment of TS cells along D (plus a halo of kIg4Half
-// cells on each side) for TC lines in LDS, one variable at a time; each
-// thread owns 4 consecutive cells of a line and accumulates them with two
-// sliding register windows (about 25 LDS reads per output instead of 96).
-// Along xi 4 lines of 256 cells, along eta / zeta 16 lines (i fastest,
-// coalesced) of 64 cells.
+// MIG4 gradients (Eq. IG4_grads, read as differences, alpha = 5/14) from the
+// factorisation of the tridiagonal left-hand side: with
+// q = (1 - sqrt(1 - 4 alpha^2)) / (2 alpha), alpha E^-1 + 1 + alpha E equals
+// (alpha / q)(1 + q E^-1)(1 + q E), whose inverse on the infinite (or
+// periodically extended) line is K sum_m (-q)^|m| E^m, K = 1 / sqrt(1 - 4 alpha^2).
+// So f' = K (L + R) with two first-order recurrences over the right-hand
+// side r_k = a (f_{k+1} - f_{k-1}) + b (f_{k+2} - f_{k-2}):
+//   L_k = r_k - q L_{k-1}          (= sum_{m >= 0} (-q)^m r_{k-m}),
+//   R_k = -q (r_{k+1} + R_{k+1})   (= sum_{m >= 1} (-q)^m r_{k+m}).
+// Started 46 cells away (q^46 < 5e-18) they give the cyclic solution to FP64
+// rounding, like the explicit stencil of gbr_stencil.hip, at a few
+// operations per cell instead of a 97-point sum.
+// A workgroup stages a tile of TS cells along D plus a 48-cell halo on each
+// side for TC lines in LDS, one variable at a time. Each line of LEN = TS +
+// 96 positions is cut into NSEG segments of S positions, one per thread:
+// every thread runs both recurrences over its segment from zero, the
+// segments' end values meet in LDS, and each thread adds the carries of the
+// segments before it (L) and after it (R), weighted by powers of (-q)^S,
+// over the segments that reach it above 1e-18. Long tiles keep the halo
+// share small: along xi 8 lines of 416 cells (32 segments of 16), along
+// eta / zeta 16 lines (i fastest, coalesced) of 192 cells (16 segments of
+// 18); lines shorter than a tile are staged around their period.
 template <int D>
-struct Ig4Tile {
-    static constexpr int TC = (D == 0) ? 4 : 16;
-    static constexpr int TS = (D == 0) ? 256 : 64;
+struct Ig4RecTile {
+    static constexpr int H = kIg4Half;
+    static constexpr int TS = (D == 0) ? 416 : 192;
+    static constexpr int TC = (D == 0) ? 8 : 16;
+    static constexpr int LEN = TS + 2 * H;
+    static constexpr int S = (D == 0) ? 16 : 18;
+    static constexpr int NSEG = LEN / S;
+    static_assert(NSEG * S == LEN && NSEG * TC == 256, "one segment per thread");
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
     static constexpr int OD = (D == 2) ? 1 : 2;
-    static constexpr int LEN = TS + 2 * kIg4Half;
-    static_assert(D != 0 || LEN % 4 == 0, "xi lines are stored in four quarter-rows");
-    // LDS position of (s, c). Along eta / zeta c is contiguous. Along xi a
-    // thread owns cells 4 sq .. 4 sq + 3, so cell s of a line sits in
-    // quarter-row s % 4 at position s / 4: for every window read the 64 lanes
-    // of a wavefront then touch consecutive words (plain rows would put them
-    // 32 bytes apart, an 8-way bank conflict).
-    __device__ static constexpr int at(int sl, int cl)
-    {
-        return D == 0 ? cl * LEN + (sl & 3) * (LEN / 4) + (sl >> 2) : sl * TC + cl;
-    }
-    // offset of cell 4 sq + k from cell 4 sq of the same line (k >= 0)
-    __device__ static constexpr int off(int k) { return D == 0 ? (k & 3) * (LEN / 4) + (k >> 2) : k * TC; }
+    // LDS position of (s, c): rows along s for xi, c fastest otherwise
+    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * LEN + sl : sl * TC + cl; }
+    // thread -> (line, segment)
+    __device__ static constexpr int line_of(int tid) { return D == 0 ? tid / NSEG : tid % TC; }
+    __device__ static constexpr int seg_of(int tid) { return D == 0 ? tid % NSEG : tid / TC; }
 };
 
 template <int D, int NDIM, class R>
-__global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st)
+__global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
 {
-    using T = Ig4Tile<D>;
-    constexpr int H = kIg4Half, TS = T::TS, TC = T::TC, LEN = T::LEN;
-    static_assert(TC * (TS / 4) == kBlock, "four cells per thread");
+    using T = Ig4RecTile<D>;
+    constexpr int H = T::H, TS = T::TS, TC = T::TC, LEN = T::LEN, S = T::S, NSEG = T::NSEG;
+    constexpr int CARRY = (H - 2 + S - 1) / S;  // segments whose end values reach a segment above q^46
     __shared__ R buf[LEN * TC];
+    __shared__ R endL[TC * NSEG], endR[TC * NSEG];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
@@ -206,54 +214,81 @@ __global__ void __launch_bounds__(kBlock) k_ig4_grad(RhsArgs<R> a, Ig4Stencil st
     const int c0 = (blockIdx.x / tiles_s) * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
-    // this thread: cells 4 sq .. 4 sq + 3 of line cl
-    const int cl = (D == 0) ? tid / (TS / 4) : tid % TC;
-    const int sq = (D == 0) ? tid % (TS / 4) : tid / TC;
+    const int cl = T::line_of(tid), sg = T::seg_of(tid);
+    const int p0 = sg * S;  // first position of this thread's segment
+    const R q = R(rc.q), K = R(rc.K), ca = R(rc.a), cb = R(rc.b), rho = R(rc.pw[S]);
     R *outs[6] = {a.grad2 + (D * 2 + 0) * N, a.grad + (D * 4 + 0) * N, a.grad + (D * 4 + 1) * N,
                   a.grad + (D * 4 + 2) * N, a.grad2 + (D * 2 + 1) * N, a.grad + (D * 4 + 3) * N};
     for (int v = 0; v < 6; ++v) {
-        R acc[4] = {R(0), R(0), R(0), R(0)};
-        if (!(NDIM == 2 && v == 3)) {  // w is identically zero in 2-D
-            const R *f = a.prim + (long)v * N;
-            for (int e = tid; e < LEN * TC; e += kBlock) {
-                const int sl = (D == 0) ? e % LEN : e / TC;
-                const int cc = (D == 0) ? e / LEN : e % TC;
-                buf[T::at(sl, cc)] =
-                    f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cc, nc - 1), o)];
+        if (NDIM == 2 && v == 3) {  // w is identically zero in 2-D
+            for (int e = tid; e < TS * TC; e += kBlock) {
+                const int sl = (D == 0) ? e % TS : e / TC;
+                const int cc = (D == 0) ? e / TS : e % TC;
+                if (s0 + sl < ns && c0 + cc < nc) outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cc, o)] = R(0);
             }
-            __syncthreads();
-            // sliding windows: at step j, P[q] = f(4 sq + q + j) and
-            // M[q] = f(4 sq + q - j); each step loads one new value per side
-            const R *c = buf + T::at(4 * sq, cl);  // cell 4 sq + k at c[T::off(k)]
-            R P[4], M[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                P[q] = c[T::off(H + q + 1)];
-                M[q] = c[T::off(H + q - 1)];
-            }
-#pragma unroll GBR_IG4_UNROLL
-            for (int j = 1; j <= H; ++j) {
-                const R w = R(st.w[j]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] += w * (P[q] - M[q]);
-                if (j < H) {
-                    P[0] = P[1];
-                    P[1] = P[2];
-                    P[2] = P[3];
-                    P[3] = c[T::off(H + 4 + j)];
-                    M[3] = M[2];
-                    M[2] = M[1];
-                    M[1] = M[0];
-                    M[0] = c[T::off(H - 1 - j)];
-                }
-            }
-            __syncthreads();
+            continue;
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int sl = 4 * sq + q;
-            if (s0 + sl < ns && c0 + cl < nc) outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cl, o)] = acc[q];
+        const R *f = a.prim + (long)v * N;
+        for (int e = tid; e < LEN * TC; e += kBlock) {
+            const int sl = (D == 0) ? e % LEN : e / TC;
+            const int cc = (D == 0) ? e / LEN : e % TC;
+            buf[T::at(sl, cc)] = f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cc, nc - 1), o)];
         }
+        __syncthreads();
+        // forward recurrence over the segment from zero, the right-hand sides
+        // from a sliding window (positions within two of the staged ends have
+        // none); only L is kept: r_k = L_k + q L_{k-1} recovers the
+        // right-hand sides for the backward passes
+        auto F = [&](int p) { return buf[T::at(min(max(p, 0), LEN - 1), cl)]; };
+        R Ll[S];
+        R fm2 = F(p0 - 2), fm1 = F(p0 - 1), f0 = F(p0), fp1 = F(p0 + 1);
+        R L = R(0), rnext = R(0);
+#pragma unroll
+        for (int t = 0; t <= S; ++t) {
+            const int p = p0 + t;
+            const R fp2 = F(p + 2);
+            const R r = (p >= 2 && p <= LEN - 3) ? ca * (fp1 - fm1) + cb * (fp2 - fm2) : R(0);
+            if (t < S) {
+                L = r - q * L;
+                Ll[t] = L;
+            } else {
+                rnext = r;
+            }
+            fm2 = fm1;
+            fm1 = f0;
+            f0 = fp1;
+            fp1 = fp2;
+        }
+        auto rhs_at = [&](int t) { return t == 0 ? Ll[0] : Ll[t] + q * Ll[t - 1]; };
+        // backward recurrence from zero: only its value at the segment start
+        R Rr = R(0);
+#pragma unroll
+        for (int t = S - 1; t >= 0; --t) Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
+        endL[cl * NSEG + sg] = L;   // L at the segment's last position, from zero
+        endR[cl * NSEG + sg] = Rr;  // R at the segment's first position, from zero
+        __syncthreads();
+        // carries: true L before the segment, true R after it
+        R cin = R(0), cout = R(0);
+#pragma unroll
+        for (int m = CARRY; m >= 1; --m) {
+            cin = rho * cin + ((sg - m >= 0) ? endL[cl * NSEG + sg - m] : R(0));
+            cout = rho * cout + ((sg + m < NSEG) ? endR[cl * NSEG + sg + m] : R(0));
+        }
+        // true R backwards from the carry, true L in closed form from the carry
+        Rr = cout;
+#pragma unroll
+        for (int t = S - 1; t >= 0; --t) {
+            Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
+            buf[T::at(p0 + t, cl)] = K * ((Ll[t] + R(rc.pw[t + 1]) * cin) + Rr);
+        }
+        __syncthreads();
+        for (int e = tid; e < TS * TC; e += kBlock) {
+            const int sl = (D == 0) ? e % TS : e / TC;
+            const int cc = (D == 0) ? e / TS : e % TC;
+            if (s0 + sl < ns && c0 + cc < nc)
+                outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cc, o)] = buf[T::at(H + sl, cc)];
+        }
+        __syncthreads();
     }
 }
 
@@ -1028,12 +1063,12 @@ __global__ void __launch_bounds__(64) k_diag_final(const double *partial, int nb
 }
 
 template <int D, int NDIM, class R>
-void ig4_grad(gbr_grid_s *g, const RhsArgs<R> &a, const Ig4Stencil &st)
+void ig4_grad(gbr_grid_s *g, const RhsArgs<R> &a)
 {
-    using T = Ig4Tile<D>;
+    using T = Ig4RecTile<D>;
     const int ns = a.dm.n[T::SD], nc = a.dm.n[T::CD], no = a.dm.n[T::OD];
     dim3 grid(unsigned(((ns + T::TS - 1) / T::TS) * ((nc + T::TC - 1) / T::TC)), unsigned(no));
-    hipLaunchKernelGGL((k_ig4_grad<D, NDIM, R>), grid, dim3(kBlock), 0, g->stream, a, st);
+    hipLaunchKernelGGL((k_ig4_rec<D, NDIM, R>), grid, dim3(kBlock), 0, g->stream, a, ig4_rec());
 }
 
 // One RHS: primitives of Q (unless given), cell gradients and sensor, the
@@ -1055,10 +1090,9 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
         // reconstruction as well), then the sensor from them
         {
             Timed timed(g, GBR_K_CELL_GRAD);
-            const Ig4Stencil &st = ig4_stencil();
-            ig4_grad<0, NDIM, R>(g, a, st);
-            ig4_grad<1, NDIM, R>(g, a, st);
-            if (NDIM == 3) ig4_grad<NDIM == 3 ? 2 : 1, NDIM, R>(g, a, st);
+            ig4_grad<0, NDIM, R>(g, a);
+            ig4_grad<1, NDIM, R>(g, a);
+            if (NDIM == 3) ig4_grad<NDIM == 3 ? 2 : 1, NDIM, R>(g, a);
             if (a.pr.limiter == GBR_LIM_DUCROS)
                 hipLaunchKernelGGL((k_sensor<NDIM, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
         }
@@ -1138,14 +1172,13 @@ hipError_t diag_typed(gbr_grid_s *g, const double *Q, double *fields, double *in
     else
         hipLaunchKernelGGL((k_prims<2, R>), dim3(blocks), dim3(kBlock), 0, g->stream, a);
     if (ig4) {
-        const Ig4Stencil &st = ig4_stencil();
         if (nd == 3) {
-            ig4_grad<0, 3, R>(g, a, st);
-            ig4_grad<1, 3, R>(g, a, st);
-            ig4_grad<2, 3, R>(g, a, st);
+            ig4_grad<0, 3, R>(g, a);
+            ig4_grad<1, 3, R>(g, a);
+            ig4_grad<2, 3, R>(g, a);
         } else {
-            ig4_grad<0, 2, R>(g, a, st);
-            ig4_grad<1, 2, R>(g, a, st);
+            ig4_grad<0, 2, R>(g, a);
+            ig4_grad<1, 2, R>(g, a);
         }
     } else {
         using GT = GradTile<R>;
@@ -1324,7 +1357,6 @@ hipError_t launch_copy(gbr_grid_s *g, double *dst, const double *src, long n)
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, g->stream, dst, src, n);
     return hipGetLastError();
 }
-
 
 hipError_t launch_step_time(gbr_grid_s *g, const double *dt, double *dt_out, double *t)
 {

@@ -34,6 +34,23 @@ const Ig4Stencil &ig4_stencil()
     return s;
 }
 
+const Ig4Rec &ig4_rec()
+{
+    static const Ig4Rec r = [] {
+        Ig4Rec t{};
+        const double al = 5.0 / 14.0;
+        const double s = std::sqrt(1.0 - 4.0 * al * al);
+        t.q = (1.0 - s) / (2.0 * al);
+        t.K = 1.0 / s;
+        t.a = 2.0 * (2.0 + al) / 6.0;
+        t.b = (4.0 * al - 1.0) / 12.0;
+        t.pw[0] = 1.0;
+        for (int j = 1; j < 20; ++j) t.pw[j] = t.pw[j - 1] * (-t.q);
+        return t;
+    }();
+    return r;
+}
+
 const Ig4MetricStencil &ig4_metric_stencil()
 {
     static const Ig4MetricStencil s = [] {
