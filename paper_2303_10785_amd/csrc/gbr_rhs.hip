@@ -426,17 +426,10 @@ struct Tile {
     static constexpr int NP = TS + 11;  // primitive cells s0-6 .. s0+TS+4
     static constexpr int N1 = TS + 5;   // first derivatives s0-3 .. s0+TS+1
     static constexpr int N2 = TS + 3;   // second derivatives s0-2 .. s0+TS
-    // Row pitch of the eta / zeta arrays (c fastest): one word more than the
-    // TC lanes of a row, so that lanes at the same cross position and
-    // different interfaces (as the Ducros gather mixes them) fall into
-    // different LDS banks; the xi arrays keep rows of ns along s.
-    static constexpr int RP = (D == 0) ? TC : TC + 1;
-    static constexpr int ST = (D == 0) ? 1 : RP;  // LDS stride between cells along D
-    // Array strides (elements between variables) and the flux-exchange stride.
-    static constexpr int VPS = NP * RP, V1S = N1 * RP, V2S = N2 * RP, FVS = TS * RP;
+    static constexpr int ST = (D == 0) ? 1 : TC;  // LDS stride between cells along D
     // LDS offset of (s, c) in an array with ns entries along s: s fastest for
     // the xi sweep (lanes run along s), c fastest otherwise (lanes run along c).
-    __device__ static constexpr int at(int s, int c, int ns) { return D == 0 ? c * ns + s : s * RP + c; }
+    __device__ static constexpr int at(int s, int c, int ns) { return D == 0 ? c * ns + s : s * TC + c; }
     // thread id -> (interface index along D, cross lane)
     __device__ static constexpr int t_of(int tid) { return D == 0 ? tid % TS : tid / TC; }
     __device__ static constexpr int c_of(int tid) { return D == 0 ? tid / TS : tid % TC; }
@@ -462,8 +455,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
 {
     using T = Tile<D, TSO>;
     constexpr int TS = T::TS, TC = T::TC, NP = T::NP, N1 = T::N1, N2 = T::N2, st = T::ST;
-    constexpr int VP = T::VPS, V1 = T::V1S, V2 = T::V2S, FV = T::FVS;  // strides between variables
-    constexpr int CP = NP * TC, C1 = N1 * TC, C2 = N2 * TC;          // elements per variable
+    constexpr int VP = NP * TC, V1 = N1 * TC, V2 = N2 * TC;
 
     const Dims &dm = a.dm;
     const PhysR<R> &ph = a.pr;
@@ -480,7 +472,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     // priority is raised while it requests them, so that a new tile's loads
     // go out ahead of the arithmetic of the other tiles on the SIMD.
     __builtin_amdgcn_s_setprio(2);
-    for (int e = tid; e < CP; e += kBlock) {
+    for (int e = tid; e < VP; e += kBlock) {
         int sl = (D == 0) ? e % NP : e / TC;
         int cl = (D == 0) ? e / NP : e % TC;
         int sg = wrap_index(s0 - 6 + sl, ns);
@@ -494,7 +486,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     __syncthreads();
     // Phase 2: first derivatives of cells s0-3 .. s0+TS+1: E6 from the LDS
     // pencils (MEG6), or the stored IG4 gradients (MIG4)
-    for (int e = tid; e < C1; e += kBlock) {
+    for (int e = tid; e < V1; e += kBlock) {
         int sl = (D == 0) ? e % N1 : e / TC;
         int cl = (D == 0) ? e / N1 : e % TC;
         int at = T::at(sl, cl, N1);
@@ -516,7 +508,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     }
     __syncthreads();
     // Hermite second derivatives (Step-1) of cells s0-2 .. s0+TS, once per cell
-    for (int e = tid; e < C2; e += kBlock) {
+    for (int e = tid; e < V2; e += kBlock) {
         int sl = (D == 0) ? e % N2 : e / TC;
         int cl = (D == 0) ? e / N2 : e % TC;
         int pc = T::at(sl + 4, cl, NP);
@@ -722,7 +714,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     __syncthreads();
     // interface fluxes back to LDS (reusing the primitive buffer)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sP[v * FV + T::at(t, cl, TS)] = phi[v];
+    for (int v = 0; v < 5; ++v) sP[v * kBlock + T::at(t, cl, TS)] = phi[v];
     __syncthreads();
     // Phase 4: Res of cell s0+t from its two interfaces (Sec. 3, Step-7)
     if (own) {
@@ -731,7 +723,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         for (int v = 0; v < 5; ++v) {
             if (NDIM == 2 && v == 3) continue;
             const int ov = (NDIM == 2 && v == 4) ? 3 : v;
-            const R d = sP[v * FV + T::at(th + 1, clh, TS)] - sP[v * FV + T::at(th, clh, TS)];
+            const R d = sP[v * kBlock + T::at(th + 1, clh, TS)] - sP[v * kBlock + T::at(th, clh, TS)];
             R *r = a.res + (long)ov * N + ch;
             if (MODE == 0) {
                 *r = interior ? -d : R(0);  // Res is zero in ghost cells
@@ -783,9 +775,9 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a, int tiles_s, int main_blo
 {
     using T0 = Tile<D>;
     using T1 = Tile<D, TAIL ? TAIL : T0::TS>;
-    __shared__ R sP[5 * cmax(T0::VPS, T1::VPS)];
-    __shared__ R s1[5 * cmax(T0::V1S, T1::V1S)];
-    __shared__ R s2[5 * cmax(T0::V2S, T1::V2S)];
+    __shared__ R sP[5 * cmax(T0::NP * T0::TC, T1::NP * T1::TC)];
+    __shared__ R s1[5 * cmax(T0::N1 * T0::TC, T1::N1 * T1::TC)];
+    __shared__ R s2[5 * cmax(T0::N2 * T0::TC, T1::N2 * T1::TC)];
     __shared__ int s_order[kBlock];
     __shared__ int s_count[kBlock / 64];
     if (TAIL == 0 || (int)blockIdx.x < main_blocks)
