@@ -191,8 +191,13 @@ struct Ig4RecTile {
     static constexpr int SD = D;
     static constexpr int CD = (D == 0) ? 1 : 0;
     static constexpr int OD = (D == 2) ? 1 : 2;
-    // LDS position of (s, c): rows along s for xi, c fastest otherwise
-    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * LEN + sl : sl * TC + cl; }
+    // Along xi the threads of a line walk their segments side by side, so a
+    // row keeps one spare word after every segment (segment starts then fall
+    // into different LDS banks); eta / zeta rows are c fastest.
+    static constexpr int ROW = LEN + NSEG;
+    static constexpr int BUF = (D == 0) ? ROW * TC : LEN * TC;
+    // LDS position of (s, c)
+    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * ROW + sl + sl / S : sl * TC + cl; }
     // thread -> (line, segment)
     __device__ static constexpr int line_of(int tid) { return D == 0 ? tid / NSEG : tid % TC; }
     __device__ static constexpr int seg_of(int tid) { return D == 0 ? tid % NSEG : tid / TC; }
@@ -204,8 +209,11 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     using T = Ig4RecTile<D>;
     constexpr int H = T::H, TS = T::TS, TC = T::TC, LEN = T::LEN, S = T::S, NSEG = T::NSEG;
     constexpr int CARRY = (H - 2 + S - 1) / S;  // segments whose end values reach a segment above q^46
-    __shared__ R buf[LEN * TC];
-    __shared__ R endL[TC * NSEG], endR[TC * NSEG];
+    __shared__ R buf[T::BUF];
+    // segment end values, [line][segment] with a spare word per line so that
+    // the lines of one segment index fall into different banks
+    constexpr int EP = NSEG + 1;
+    __shared__ R endL[TC * EP], endR[TC * EP];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
@@ -264,15 +272,15 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
         R Rr = R(0);
 #pragma unroll
         for (int t = S - 1; t >= 0; --t) Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
-        endL[cl * NSEG + sg] = L;   // L at the segment's last position, from zero
-        endR[cl * NSEG + sg] = Rr;  // R at the segment's first position, from zero
+        endL[cl * EP + sg] = L;   // L at the segment's last position, from zero
+        endR[cl * EP + sg] = Rr;  // R at the segment's first position, from zero
         __syncthreads();
         // carries: true L before the segment, true R after it
         R cin = R(0), cout = R(0);
 #pragma unroll
         for (int m = CARRY; m >= 1; --m) {
-            cin = rho * cin + ((sg - m >= 0) ? endL[cl * NSEG + sg - m] : R(0));
-            cout = rho * cout + ((sg + m < NSEG) ? endR[cl * NSEG + sg + m] : R(0));
+            cin = rho * cin + ((sg - m >= 0) ? endL[cl * EP + sg - m] : R(0));
+            cout = rho * cout + ((sg + m < NSEG) ? endR[cl * EP + sg + m] : R(0));
         }
         // true R backwards from the carry, true L in closed form from the carry
         Rr = cout;
