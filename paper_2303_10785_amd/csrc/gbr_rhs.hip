@@ -227,6 +227,36 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     const R q = R(rc.q), K = R(rc.K), ca = R(rc.a), cb = R(rc.b), rho = R(rc.pw[S]);
     R *outs[6] = {a.grad2 + (D * 2 + 0) * N, a.grad + (D * 4 + 0) * N, a.grad + (D * 4 + 1) * N,
                   a.grad + (D * 4 + 2) * N, a.grad2 + (D * 2 + 1) * N, a.grad + (D * 4 + 3) * N};
+    // Staging with light index arithmetic: element e = tid + q kBlock of the
+    // tile. Along eta / zeta its cross lane is fixed (tid % TC) and its
+    // position along the line advances by kBlock / TC per q; along xi a line
+    // of LEN = 2 kBlock positions takes two q per line, so each thread has
+    // two positions along s and one line per pair of q. The periodic wrap is
+    // applied once and then advanced by subtraction.
+    static_assert(D != 0 || LEN == 2 * kBlock, "xi rows of two blocks");
+    const long sd_stride = (T::SD == 0) ? 1 : (T::SD == 1 ? (long)dm.n[0] : (long)dm.n[0] * dm.n[1]);
+    auto stage = [&](const R *f) {
+        if (D == 0) {
+            const int s_a = wrap_index(s0 - H + tid, ns);
+            const int s_b = wrap_index(s0 - H + tid + kBlock, ns);
+#pragma unroll 4
+            for (int cc = 0; cc < TC; ++cc) {
+                const long base = cell_of(dm, T::SD, T::CD, 0, min(c0 + cc, nc - 1), o);
+                buf[T::at(tid, cc)] = f[base + s_a];
+                buf[T::at(tid + kBlock, cc)] = f[base + s_b];
+            }
+        } else {
+            constexpr int STEP = kBlock / TC;
+            const int cc = tid % TC;
+            const long base = cell_of(dm, T::SD, T::CD, 0, min(c0 + cc, nc - 1), o);
+            int sl = tid / TC, sg_ = wrap_index(s0 - H + sl, ns);
+            for (; sl < LEN; sl += STEP) {
+                buf[T::at(sl, cc)] = f[base + sg_ * sd_stride];
+                sg_ += STEP;
+                while (sg_ >= ns) sg_ -= ns;
+            }
+        }
+    };
     for (int v = 0; v < 6; ++v) {
         if (NDIM == 2 && v == 3) {  // w is identically zero in 2-D
             for (int e = tid; e < TS * TC; e += kBlock) {
@@ -237,11 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
             continue;
         }
         const R *f = a.prim + (long)v * N;
-        for (int e = tid; e < LEN * TC; e += kBlock) {
-            const int sl = (D == 0) ? e % LEN : e / TC;
-            const int cc = (D == 0) ? e / LEN : e % TC;
-            buf[T::at(sl, cc)] = f[cell_of(dm, T::SD, T::CD, wrap_index(s0 - H + sl, ns), min(c0 + cc, nc - 1), o)];
-        }
+        stage(f);
         __syncthreads();
         // forward recurrence over the segment from zero, the right-hand sides
         // from a sliding window (positions within two of the staged ends have
