@@ -15,6 +15,11 @@ __device__ __forceinline__ int wrap_index(int a, int n)
     return r < 0 ? r + n : r;
 }
 
+// wrap_index for indices that leave [0, n) only when `edge` is set; tiles
+// away from the ends of their lines (edge false, uniform across a
+// workgroup) skip the modulo.
+__device__ __forceinline__ int wrap_if(bool edge, int a, int n) { return edge ? wrap_index(a, n) : a; }
+
 // Number of periods crossed going from [0, n) to index a (floor(a / n)).
 __device__ __forceinline__ int wrap_count(int a, int n)
 {

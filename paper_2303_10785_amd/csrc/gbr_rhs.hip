@@ -382,11 +382,14 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
     const bool inside = i < ni && j < nj;
     const int ic = min(i, ni - 1), jc = min(j, nj - 1);
     const R *f[4] = {a.prim + N, a.prim + 2 * N, a.prim + 3 * N, a.prim + 5 * N};
+    // halos leave the grid only for tiles at the ends of their lines
+    const bool edge_ij = i0 < 3 || i0 + GI + 3 > ni || j0 < 3 || j0 + GJ + 3 > nj;
+    const bool edge_k = k0 < 3 || k0 + KC + 3 > nk;
     R win[7][4];
     if (NDIM == 3) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            const long c = pack(dm, ic, jc, wrap_index(k0 - 3 + q, nk));
+            const long c = pack(dm, ic, jc, wrap_if(edge_k, k0 - 3 + q, nk));
 #pragma unroll
             for (int s = 0; s < 4; ++s) win[q][s] = f[s][c];
         }
@@ -398,7 +401,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
         R mt[3][3];
         if (SENSOR) load_unhat(a.m, N, pack(dm, ic, jc, k), mt);
         if (NDIM == 3) {
-            const long c = pack(dm, ic, jc, wrap_index(k + 3, nk));
+            const long c = pack(dm, ic, jc, wrap_if(edge_k, k + 3, nk));
 #pragma unroll
             for (int s = 0; s < 4; ++s) win[6][s] = f[s][c];
             // the tile's own cells of plane k are already in the register
@@ -413,7 +416,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
             const int x = e % HI, y = e / HI;
             const int gi = i0 - 3 + x, gj = j0 - 3 + y;
             if (NDIM == 3 && x >= 3 && x < GI + 3 && y >= 3 && y < GJ + 3 && gi < ni && gj < nj) continue;
-            const long c = pack(dm, wrap_index(gi, ni), wrap_index(gj, nj), k);
+            const long c = pack(dm, wrap_if(edge_ij, gi, ni), wrap_if(edge_ij, gj, nj), k);
 #pragma unroll
             for (int s = 0; s < 4; ++s) sp[s][y][x] = f[s][c];
         }
@@ -501,6 +504,9 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const int c0 = tcb * TC;
     const int o = blockIdx.y;
     const int tid = threadIdx.x;
+    // every cell this tile touches along D (s0 - 6 .. s0 + TS + 4) lies in
+    // [0, ns) unless the tile sits at an end of its line
+    const bool edge = s0 < 6 || s0 + TS + 5 > ns;
 
     // Phase 1: primitives of cells s0-6 .. s0+TS+4 into LDS. The wave's issue
     // priority is raised while it requests them, so that a new tile's loads
@@ -509,7 +515,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     for (int e = tid; e < VP; e += kBlock) {
         int sl = (D == 0) ? e % NP : e / TC;
         int cl = (D == 0) ? e / NP : e % TC;
-        int sg = wrap_index(s0 - 6 + sl, ns);
+        int sg = wrap_if(edge, s0 - 6 + sl, ns);
         int cg = min(c0 + cl, nc - 1);
         long c = cell_of(dm, T::SD, T::CD, sg, cg, o);
         int at = T::at(sl, cl, NP);
@@ -525,7 +531,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         int cl = (D == 0) ? e / N1 : e % TC;
         int at = T::at(sl, cl, N1);
         if (IG4) {
-            const long c = cell_of(dm, T::SD, T::CD, wrap_index(s0 - 3 + sl, ns), min(c0 + cl, nc - 1), o);
+            const long c = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 - 3 + sl, ns), min(c0 + cl, nc - 1), o);
             s1[0 * V1 + at] = a.grad2[(D * 2 + 0) * N + c];
             s1[1 * V1 + at] = a.grad[(D * 4 + 0) * N + c];
             s1[2 * V1 + at] = a.grad[(D * 4 + 1) * N + c];
@@ -572,8 +578,8 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     if (compact && ph.limiter == GBR_LIM_DUCROS) {
         const int t0 = T::t_of(tid), cl0 = T::c_of(tid);
         const int cg0 = min(c0 + cl0, nc - 1);
-        const long a0 = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t0 - 1, ns), cg0, o);
-        const long b0 = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t0, ns), cg0, o);
+        const long a0 = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t0 - 1, ns), cg0, o);
+        const long b0 = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t0, ns), cg0, o);
         const bool mine = fmax(a.theta[a0], a.theta[b0]) > ph.theta_c;
         const unsigned long long bal = __ballot(mine);
         const int lane = tid % 64, wave = tid / 64;
@@ -597,8 +603,8 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const int cl = T::c_of(f);
     const int cg = c0 + cl;
     const int cgc = min(cg, nc - 1);
-    const long ca = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t - 1, ns), cgc, o);
-    const long cb = cell_of(dm, T::SD, T::CD, wrap_index(s0 + t, ns), cgc, o);
+    const long ca = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t - 1, ns), cgc, o);
+    const long cb = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t, ns), cgc, o);
     const R *Pa = sP + T::at(t + 5, cl, NP);
     const R *Ga = s1 + T::at(t + 2, cl, N1);
     const R *Ha = s2 + T::at(t + 1, cl, N2);
