@@ -193,11 +193,30 @@ struct Ig4RecTile {
     static constexpr int OD = (D == 2) ? 1 : 2;
     // Along xi the threads of a line walk their segments side by side, so a
     // row keeps one spare word after every segment (segment starts then fall
-    // into different LDS banks); eta / zeta rows are c fastest.
+    // into different LDS banks), and four spare words before and after the
+    // rows take the window's reach two positions past the line ends (the
+    // values read there only enter right-hand sides that are zero). Eta /
+    // zeta rows are c fastest and their end segments clamp the window
+    // instead, which keeps the workgroup within 40 KB of LDS.
     static constexpr int ROW = LEN + NSEG;
-    static constexpr int BUF = (D == 0) ? ROW * TC : LEN * TC;
-    // LDS position of (s, c)
-    __device__ static constexpr int at(int sl, int cl) { return D == 0 ? cl * ROW + sl + sl / S : sl * TC + cl; }
+    static constexpr int BUF = (D == 0) ? ROW * TC + 8 : LEN * TC;
+    // LDS position of (s, c), 0 <= s < LEN
+    __device__ static constexpr int at(int sl, int cl)
+    {
+        return D == 0 ? 4 + cl * ROW + sl + sl / S : sl * TC + cl;
+    }
+    // offset of position p0 + t from at(p0, c) for a segment start p0,
+    // -2 <= t <= S + 2 (along eta / zeta only inside the staged line)
+    __device__ static constexpr int rel(int t) { return D == 0 ? t + (t < 0 ? -1 : t / S) : t * TC; }
+    // segment end values: along xi [line][segment] with a spare word per
+    // line, along eta / zeta [segment][line]; L of the last segment and R of
+    // the first are never read and not stored there
+    static constexpr int NEND = (D == 0) ? TC * (NSEG + 1) : (NSEG - 1) * TC;
+    __device__ static constexpr int endl_at(int sg, int cl) { return D == 0 ? cl * (NSEG + 1) + sg : sg * TC + cl; }
+    __device__ static constexpr int endr_at(int sg, int cl)
+    {
+        return D == 0 ? cl * (NSEG + 1) + sg : (sg - 1) * TC + cl;
+    }
     // thread -> (line, segment)
     __device__ static constexpr int line_of(int tid) { return D == 0 ? tid / NSEG : tid % TC; }
     __device__ static constexpr int seg_of(int tid) { return D == 0 ? tid % NSEG : tid / TC; }
@@ -210,10 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     constexpr int H = T::H, TS = T::TS, TC = T::TC, LEN = T::LEN, S = T::S, NSEG = T::NSEG;
     constexpr int CARRY = (H - 2 + S - 1) / S;  // segments whose end values reach a segment above q^46
     __shared__ R buf[T::BUF];
-    // segment end values, [line][segment] with a spare word per line so that
-    // the lines of one segment index fall into different banks
-    constexpr int EP = NSEG + 1;
-    __shared__ R endL[TC * EP], endR[TC * EP];
+    __shared__ R endL[T::NEND], endR[T::NEND];
     const Dims &dm = a.dm;
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
@@ -224,6 +240,11 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     const int tid = threadIdx.x;
     const int cl = T::line_of(tid), sg = T::seg_of(tid);
     const int p0 = sg * S;  // first position of this thread's segment
+    if constexpr (D == 0) {
+        // clear the spare words before and after the rows (read, never used)
+        if (tid < 4) buf[tid] = R(0);
+        if (tid < 4) buf[T::BUF - 4 + tid] = R(0);
+    }
     const R q = R(rc.q), K = R(rc.K), ca = R(rc.a), cb = R(rc.b), rho = R(rc.pw[S]);
     R *outs[6] = {a.grad2 + (D * 2 + 0) * N, a.grad + (D * 4 + 0) * N, a.grad + (D * 4 + 1) * N,
                   a.grad + (D * 4 + 2) * N, a.grad2 + (D * 2 + 1) * N, a.grad + (D * 4 + 3) * N};
@@ -236,27 +257,78 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     static_assert(D != 0 || LEN == 2 * kBlock, "xi rows of two blocks");
     const long sd_stride = (T::SD == 0) ? 1 : (T::SD == 1 ? (long)dm.n[0] : (long)dm.n[0] * dm.n[1]);
     auto stage = [&](const R *f) {
-        if (D == 0) {
+        if constexpr (D == 0) {
             const int s_a = wrap_index(s0 - H + tid, ns);
             const int s_b = wrap_index(s0 - H + tid + kBlock, ns);
-#pragma unroll 4
+            R va[TC], vb[TC];
+#pragma unroll
             for (int cc = 0; cc < TC; ++cc) {
                 const long base = cell_of(dm, T::SD, T::CD, 0, min(c0 + cc, nc - 1), o);
-                buf[T::at(tid, cc)] = f[base + s_a];
-                buf[T::at(tid + kBlock, cc)] = f[base + s_b];
+                va[cc] = f[base + s_a];
+                vb[cc] = f[base + s_b];
+            }
+#pragma unroll
+            for (int cc = 0; cc < TC; ++cc) {
+                buf[T::at(tid, cc)] = va[cc];
+                buf[T::at(tid + kBlock, cc)] = vb[cc];
             }
         } else {
             constexpr int STEP = kBlock / TC;
+            constexpr int NE = LEN / STEP;
+            static_assert(NE * STEP == LEN, "whole staging rounds");
             const int cc = tid % TC;
             const long base = cell_of(dm, T::SD, T::CD, 0, min(c0 + cc, nc - 1), o);
-            int sl = tid / TC, sg_ = wrap_index(s0 - H + sl, ns);
-            for (; sl < LEN; sl += STEP) {
-                buf[T::at(sl, cc)] = f[base + sg_ * sd_stride];
-                sg_ += STEP;
-                while (sg_ >= ns) sg_ -= ns;
+            const int sl0 = tid / TC;
+            int sg_ = wrap_index(s0 - H + sl0, ns);
+            if (ns >= STEP) {
+                // one conditional subtraction keeps the position in [0, ns),
+                // so the loop unrolls and all NE loads are in flight at once
+                // (the empty asm keeps the compiler from hoisting the offset
+                // sequence out of the loop over variables, which would hold
+                // NE addresses in registers for the kernel's lifetime)
+                __asm__ volatile("" : "+v"(sg_));
+                long off = sg_ * sd_stride;
+                const long step_off = STEP * sd_stride, wrap_off = ns * sd_stride;
+                R v[NE];
+#pragma unroll
+                for (int k = 0; k < NE; ++k) {
+                    v[k] = f[base + off];
+                    sg_ += STEP;
+                    off += step_off;
+                    if (sg_ >= ns) {
+                        sg_ -= ns;
+                        off -= wrap_off;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NE; ++k) buf[T::at(sl0 + k * STEP, cc)] = v[k];
+            } else {
+                for (int sl = sl0; sl < LEN; sl += STEP) {
+                    buf[T::at(sl, cc)] = f[base + sg_ * sd_stride];
+                    sg_ += STEP;
+                    while (sg_ >= ns) sg_ -= ns;
+                }
             }
         }
     };
+    // window of the segment: positions p0 - 2 .. p0 + S + 2; along eta /
+    // zeta the first segment reads position 0 for the two before it and the
+    // last reads position LEN - 1 for the three after it
+    const R *seg = buf + T::at(p0, cl);
+    auto win = [&](int t) -> const R * {
+        if constexpr (D == 0) {
+            return seg + T::rel(t);
+        } else {
+            if (t < 0) return sg == 0 ? seg : seg + T::rel(t);
+            if (t >= S) return sg == NSEG - 1 ? seg + T::rel(S - 1) : seg + T::rel(t);
+            return seg + T::rel(t);
+        }
+    };
+    // along eta / zeta each thread stores its own outputs (16 lanes of a
+    // line row are 128 contiguous bytes); along xi they go back through LDS
+    const int cgl = c0 + cl;
+    const long out_base = cell_of(dm, T::SD, T::CD, 0, min(cgl, nc - 1), o);
+#pragma unroll 1
     for (int v = 0; v < 6; ++v) {
         if (NDIM == 2 && v == 3) {  // w is identically zero in 2-D
             for (int e = tid; e < TS * TC; e += kBlock) {
@@ -273,14 +345,13 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
         // from a sliding window (positions within two of the staged ends have
         // none); only L is kept: r_k = L_k + q L_{k-1} recovers the
         // right-hand sides for the backward passes
-        auto F = [&](int p) { return buf[T::at(min(max(p, 0), LEN - 1), cl)]; };
         R Ll[S];
-        R fm2 = F(p0 - 2), fm1 = F(p0 - 1), f0 = F(p0), fp1 = F(p0 + 1);
+        R fm2 = *win(-2), fm1 = *win(-1), f0 = *win(0), fp1 = *win(1);
         R L = R(0), rnext = R(0);
 #pragma unroll
         for (int t = 0; t <= S; ++t) {
             const int p = p0 + t;
-            const R fp2 = F(p + 2);
+            const R fp2 = *win(t + 2);
             const R r = (p >= 2 && p <= LEN - 3) ? ca * (fp1 - fm1) + cb * (fp2 - fm2) : R(0);
             if (t < S) {
                 L = r - q * L;
@@ -298,31 +369,52 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
         R Rr = R(0);
 #pragma unroll
         for (int t = S - 1; t >= 0; --t) Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
-        endL[cl * EP + sg] = L;   // L at the segment's last position, from zero
-        endR[cl * EP + sg] = Rr;  // R at the segment's first position, from zero
+        // L at the segment's last position and R at its first, from zero
+        if (D == 0 || sg < NSEG - 1) endL[T::endl_at(sg, cl)] = L;
+        if (D == 0 || sg > 0) endR[T::endr_at(sg, cl)] = Rr;
         __syncthreads();
         // carries: true L before the segment, true R after it
         R cin = R(0), cout = R(0);
 #pragma unroll
         for (int m = CARRY; m >= 1; --m) {
-            cin = rho * cin + ((sg - m >= 0) ? endL[cl * EP + sg - m] : R(0));
-            cout = rho * cout + ((sg + m < NSEG) ? endR[cl * EP + sg + m] : R(0));
+            cin = rho * cin + ((sg - m >= 0) ? endL[T::endl_at(sg - m, cl)] : R(0));
+            cout = rho * cout + ((sg + m < NSEG) ? endR[T::endr_at(sg + m, cl)] : R(0));
         }
         // true R backwards from the carry, true L in closed form from the carry
         Rr = cout;
+        if constexpr (D == 0) {
 #pragma unroll
-        for (int t = S - 1; t >= 0; --t) {
-            Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
-            buf[T::at(p0 + t, cl)] = K * ((Ll[t] + R(rc.pw[t + 1]) * cin) + Rr);
+            for (int t = S - 1; t >= 0; --t) {
+                Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
+                buf[T::at(p0, cl) + T::rel(t)] = K * ((Ll[t] + R(rc.pw[t + 1]) * cin) + Rr);
+            }
+            __syncthreads();
+            for (int e = tid; e < TS * TC; e += kBlock) {
+                const int sl = e % TS;
+                const int cc = e / TS;
+                if (s0 + sl < ns && c0 + cc < nc)
+                    outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cc, o)] = buf[T::at(H + sl, cc)];
+            }
+            __syncthreads();
+        } else {
+            // positions H .. H + TS - 1 of the line are the tile's cells
+            // s0 .. s0 + TS - 1; the next variable's staging may overwrite
+            // buf at once, since every thread has passed its window reads
+            // (cell of the segment's last position, made opaque so that the
+            // store addresses are formed here rather than held across the
+            // loop over variables)
+            int sp = s0 + p0 - H + S - 1;
+            __asm__ volatile("" : "+v"(sp));
+            R *dst = outs[v] + out_base + (long)sp * sd_stride;
+#pragma unroll
+            for (int t = S - 1; t >= 0; --t) {
+                Rr = -q * ((t == S - 1 ? rnext : rhs_at(t + 1)) + Rr);
+                if (p0 + t >= H && p0 + t < H + TS && sp < ns && cgl < nc)
+                    *dst = K * ((Ll[t] + R(rc.pw[t + 1]) * cin) + Rr);
+                --sp;
+                dst -= sd_stride;
+            }
         }
-        __syncthreads();
-        for (int e = tid; e < TS * TC; e += kBlock) {
-            const int sl = (D == 0) ? e % TS : e / TC;
-            const int cc = (D == 0) ? e / TS : e % TC;
-            if (s0 + sl < ns && c0 + cc < nc)
-                outs[v][cell_of(dm, T::SD, T::CD, s0 + sl, c0 + cc, o)] = buf[T::at(H + sl, cc)];
-        }
-        __syncthreads();
     }
 }
 
