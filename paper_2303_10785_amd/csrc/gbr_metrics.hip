@@ -52,6 +52,18 @@ __device__ __forceinline__ long step_to(const Dims &dm, const int ijk[3], int d,
     return pack(dm, t[0], t[1], t[2]);
 }
 
+// step_to for |q| <= n[d]: the neighbour then lies at most one period away,
+// so one comparison gives the period count and the index follows from the
+// cell's own (same results as step_to, without the integer divisions).
+__device__ __forceinline__ long step_near(const Dims &dm, const int ijk[3], int d, int q, long idx, long sd,
+                                         int *wraps)
+{
+    const int n = dm.n[d], a = ijk[d] + q;
+    const int w = a < 0 ? -1 : (a >= n ? 1 : 0);
+    if (wraps) *wraps = w;
+    return idx + (long)(q - w * n) * sd;
+}
+
 // Coordinate c at linear index nb (z is the zeta index in 2-D).
 __device__ __forceinline__ double coord(const MetricArgs &a, int c, long nb)
 {
@@ -112,6 +124,16 @@ __device__ __forceinline__ long stride_of(const Dims &dm, int d)
     return d == 0 ? 1 : (d == 1 ? (long)dm.n[0] : (long)dm.n[0] * dm.n[1]);
 }
 
+// Neighbour q steps along d (and the periods crossed) for windows reaching
+// at most `reach` cells: step_near when the line is at least that long
+// (uniform over the grid), step_to otherwise.
+__device__ __forceinline__ long neighbour(const Dims &dm, const int ijk[3], int d, int q, long idx, int reach,
+                                         int *wraps)
+{
+    return dm.n[d] >= reach ? step_near(dm, ijk, d, q, idx, stride_of(dm, d), wraps)
+                            : step_to(dm, ijk, d, q, wraps);
+}
+
 template <bool IG4>
 __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricStencil st)
 {
@@ -131,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) k_coord_deriv(MetricArgs a, Ig4MetricS
             a.dx[(d * 3 + c) * a.dm.ncell + idx] =
                 seam ? composite<IG4>(st, [&](int q) {
                     int wr;
-                    long nb = step_to(a.dm, ijk, d, q, &wr);
+                    long nb = neighbour(a.dm, ijk, d, q, idx, window_half<IG4>(), &wr);
                     return image_rel(coord(a, c, nb), wr, a.off[d][c], org);
                 })
                      : composite<IG4>(st, [&](int q) { return coord(a, c, idx + q * sd) - org; });
@@ -154,7 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_metrics(MetricArgs a, Ig4Metric
         if (near_seam<IG4>(a.dm, ijk, e))
             return composite<IG4>(st, [&](int q) {
                 int wr;
-                long nb = step_to(a.dm, ijk, e, q, &wr);
+                long nb = neighbour(a.dm, ijk, e, q, idx, window_half<IG4>(), &wr);
                 return fac[nb] * image_rel(coord(a, c2, nb), wr, a.off[e][c2], org);
             });
         const long se = stride_of(a.dm, e);
@@ -210,10 +232,12 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4Metric
         if (!((fmask >> f) & 1)) continue;
         long nb[10];  // MEG6 window, reused by every slot
         if (!IG4)
-            for (int q = -4; q <= 5; ++q) nb[q + 4] = step_to(a.dm, ijk, f, q, nullptr);
+            for (int q = -4; q <= 5; ++q) nb[q + 4] = neighbour(a.dm, ijk, f, q, idx, 5, nullptr);
         auto interp = [&](int slot) {
             const double *s = m + slot * N;
-            return interface<IG4>(st, [&](int q) { return IG4 ? s[step_to(a.dm, ijk, f, q, nullptr)] : s[nb[q + 4]]; });
+            return interface<IG4>(st, [&](int q) {
+                return IG4 ? s[neighbour(a.dm, ijk, f, q, idx, kIg4Half + 2, nullptr)] : s[nb[q + 4]];
+            });
         };
         for (int c = 0; c < 3; ++c) m[GBR_SLOT_FACE_HAT(f, c) * N + idx] = interp(GBR_SLOT_CELL_HAT(f, c));
         m[GBR_SLOT_FACE_HATT(f) * N + idx] = interp(GBR_SLOT_CELL_HATT(f));
