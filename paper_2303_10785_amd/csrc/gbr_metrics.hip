@@ -9,7 +9,8 @@
 //                   cell, 1/J = det[D_d x_c], J, unhatted d_c = J hat(d)_c,
 //                   temporal metrics on moving grids
 //   k_face_metrics: interface values of the 3 hatted f-metrics, hat f_t and
-//                   all 9 unhatted metrics for each family f
+//                   all 9 unhatted metrics for each family f (MEG6: from LDS
+//                   tiles, k_face_metrics_xi and k_face_metrics_tiled)
 //   k_gcl         : (1/J)_t = -sum_f [I_f hat f_t](+1/2) - [...](-1/2)
 #include "gbr_device.hpp"
 #include "gbr_internal.hpp"
@@ -304,6 +305,55 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics_tiled(MetricArgs a)
     }
 }
 
+// MEG6 interface values of the xi family from LDS tiles: a workgroup owns
+// XT interfaces along i for XC lines along j and stages the same 13 source
+// slots of cells s0-4 .. s0+XT+4 (i fastest, coalesced rows). Same formula on
+// the same values as k_face_metrics.
+constexpr int XT = 64, XC = kBlock / XT, XNP = XT + 9;
+
+__global__ void __launch_bounds__(kBlock) k_face_metrics_xi(MetricArgs a)
+{
+    __shared__ double sv[13][XC * XNP];  // [slot][line][s]
+    const Dims &dm = a.dm;
+    const long N = dm.ncell;
+    const int ns = dm.n[0], nc = dm.n[1];
+    const int tiles_s = (ns + XT - 1) / XT;
+    const int s0 = (blockIdx.x % tiles_s) * XT;
+    const int c0 = (blockIdx.x / tiles_s) * XC;
+    const int o = blockIdx.y;
+    // cells s0-4 .. s0+XT+4 lie in [0, ns) unless the tile is at a line end
+    const bool edge = s0 < 4 || s0 + XT + 5 > ns;
+    int src[13];
+    for (int c = 0; c < 3; ++c) src[c] = GBR_SLOT_CELL_HAT(0, c);
+    src[3] = GBR_SLOT_CELL_HATT(0);
+    for (int e = 0; e < 3; ++e)
+        for (int c = 0; c < 3; ++c) src[4 + e * 3 + c] = GBR_SLOT_CELL_UNHAT(e, c);
+    for (int e = threadIdx.x; e < XNP * XC; e += kBlock) {
+        const int sl = e % XNP, cl = e / XNP;
+        const int si = s0 - 4 + sl;
+        const long cell = pack(dm, edge ? wrap_index(si, ns) : si, min(c0 + cl, nc - 1), o);
+#pragma unroll
+        for (int q = 0; q < 13; ++q) sv[q][e] = a.m[(long)src[q] * N + cell];
+    }
+    __syncthreads();
+    const int tl = threadIdx.x % XT, cl = threadIdx.x / XT;
+    const int sg = s0 + tl, cg = c0 + cl;
+    if (sg >= ns || cg >= nc) return;
+    const long idx = pack(dm, sg, cg, o);
+    int dst[13];
+    for (int c = 0; c < 3; ++c) dst[c] = GBR_SLOT_FACE_HAT(0, c);
+    dst[3] = GBR_SLOT_FACE_HATT(0);
+    for (int e = 0; e < 3; ++e)
+        for (int c = 0; c < 3; ++c) dst[4 + e * 3 + c] = GBR_SLOT_FACE_UNHAT(0, e, c);
+#pragma unroll
+    for (int q = 0; q < 13; ++q) {
+        double v[10];
+#pragma unroll
+        for (int w = 0; w < 10; ++w) v[w] = sv[q][cl * XNP + tl + w];  // cells sg-4 .. sg+5
+        a.m[(long)dst[q] * N + idx] = face_interp(v + 4);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_gcl(MetricArgs a)
 {
     long idx = blockIdx.x * (long)kBlock + threadIdx.x;
@@ -445,11 +495,13 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
     if (g->cfg.scheme == GBR_SCHEME_MIG4) {
         hipLaunchKernelGGL(k_face_metrics<true>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st, 7);
     } else {
-        // xi family per cell (its windows lie along the wavefront's own rows);
-        // eta (and zeta in 3-D) from LDS tiles
+        // every family from LDS tiles (in 2-D the trivial zeta family per cell)
         const int n0 = a.dm.n[0];
-        hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st,
-                           a.ndim == 3 ? 1 : 5);
+        hipLaunchKernelGGL(k_face_metrics_xi,
+                           dim3(unsigned(((n0 + XT - 1) / XT) * ((a.dm.n[1] + XC - 1) / XC)), unsigned(a.dm.n[2])),
+                           dim3(kBlock), 0, g->stream, a);
+        if (a.ndim == 2)
+            hipLaunchKernelGGL(k_face_metrics<false>, dim3(blocks), dim3(kBlock), 0, g->stream, a, st, 4);
         hipLaunchKernelGGL(k_face_metrics_tiled<1>,
                            dim3(unsigned(((a.dm.n[1] + FT - 1) / FT) * ((n0 + FC - 1) / FC)), unsigned(a.dm.n[2])),
                            dim3(kBlock), 0, g->stream, a);
