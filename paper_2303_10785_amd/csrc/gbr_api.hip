@@ -117,7 +117,8 @@ size_t bytes_for(const gbr_config *c)
     size_t nv = (size_t)c->ndim + 2;
     size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 12 + 2 * nv + (c->scheme == GBR_SCHEME_MIG4 ? 6 : 0)) + 1 +
                      gbr::kReducePartials;
-    return doubles * sizeof(double) + sizeof(unsigned long long) + 2 * sizeof(int);
+    const size_t floats = (c->precision == GBR_FP32_BULK) ? N * gbr::kFloatMetricSlots : 0;
+    return doubles * sizeof(double) + floats * sizeof(float) + sizeof(unsigned long long) + 2 * sizeof(int);
 }
 
 gbr_status fail(gbr_grid_s *g, gbr_status s, const char *msg)
@@ -151,7 +152,7 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->scratch, (void *)g->theta, (void *)g->grad2, (void *)g->prim,
+    for (void *p : {(void *)g->metrics, (void *)g->metrics_f, (void *)g->scratch, (void *)g->theta, (void *)g->grad2, (void *)g->prim,
                     (void *)g->prim2, (void *)g->sigma,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
@@ -201,6 +202,7 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
         if (e == hipSuccess) e = hipMalloc(p, bytes);
     };
     alloc((void **)&g->metrics, N * GBR_SLOT_COUNT * sizeof(double));
+    if (cfg->precision == GBR_FP32_BULK) alloc((void **)&g->metrics_f, N * gbr::kFloatMetricSlots * sizeof(float));
     alloc((void **)&g->scratch, N * 12 * sizeof(double));
     alloc((void **)&g->theta, N * sizeof(double));
     if (cfg->scheme == GBR_SCHEME_MIG4) alloc((void **)&g->grad2, N * 6 * sizeof(double));
@@ -214,6 +216,8 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     alloc((void **)&g->flags, 2 * sizeof(int));
     if (e == hipSuccess) e = hipMemsetAsync(g->flags, 0, 2 * sizeof(int), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(g->metrics, 0, N * GBR_SLOT_COUNT * sizeof(double), g->stream);
+    if (e == hipSuccess && g->metrics_f)
+        e = hipMemsetAsync(g->metrics_f, 0, N * gbr::kFloatMetricSlots * sizeof(float), g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
     if (e != hipSuccess) {
         gbr_status s = (e == hipErrorOutOfMemory) ? GBR_E_NOMEM : GBR_E_DEVICE;

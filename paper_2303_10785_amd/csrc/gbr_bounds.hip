@@ -504,7 +504,8 @@ hipError_t launch_metrics_bounded(gbr_grid_s *g, const double *xyz)
     hipLaunchKernelGGL(k_cell_metrics_b, dim3(blocks), dim3(kBlock), 0, g->stream, a, br);
     hipLaunchKernelGGL(k_face_metrics_b, dim3(blocks), dim3(kBlock), 0, g->stream, a, br);
     hipLaunchKernelGGL(k_metric_ghosts, dim3(blocks), dim3(kBlock), 0, g->stream, a.dm, a.m);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_metrics_float(g);
 }
 
 template <class R>

@@ -16,6 +16,11 @@ struct gbr_grid_s {
     long ncell = 0;
     int nvar = 0;
     double *metrics = nullptr;   // GBR_SLOT_COUNT * ncell
+    // FP32-bulk grids only, kFloatMetricSlots * ncell floats: the metric
+    // slots the RHS kernels read in the compute type (every face slot and the
+    // cell unhatted metrics, slots 0 .. 47), rounded once from `metrics`
+    // after each metric evaluation
+    float *metrics_f = nullptr;
     double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
     double *theta = nullptr;     // ncell: shock sensor
     double *grad2 = nullptr;     // 6 * ncell, MIG4 only: IG4 gradients of rho and p, (d * 2 + s)
@@ -80,6 +85,10 @@ struct Phys {
     int limiter;
 };
 
+// Metric slots kept in float for FP32-bulk grids (0 .. 47: the face slots
+// and the cell unhatted metrics).
+constexpr int kFloatMetricSlots = 48;
+
 // Wide explicit stencils of the MIG4 gradient and of the metric derivative
 // and interface interpolation built on it (gbr_stencil.hip).
 constexpr int kIg4Half = 48;
@@ -123,6 +132,8 @@ class Timed {
 // Kernel launchers (enqueue on g->stream; return hipSuccess or the launch error).
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t);
 hipError_t launch_metrics_nonfp(gbr_grid_s *g, const double *xyz);
+// Refresh the float metric copy of an FP32-bulk grid (no-op otherwise).
+hipError_t launch_metrics_float(gbr_grid_s *g);
 hipError_t launch_rhs(gbr_grid_s *g, const double *Q, void *res);
 hipError_t launch_rk_stage(gbr_grid_s *g, int stage, const double *dt, const double *Qn,
                            double *Q, const void *res);

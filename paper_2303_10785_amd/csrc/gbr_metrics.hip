@@ -462,7 +462,31 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics_c4(MetricArgs a)
     }
 }
 
+// Float copy of the metric slots the FP32-bulk RHS kernels read: the 13
+// interface slots of each family and the 9 cell unhatted metrics, which are
+// slots 0 .. 47, each rounded to nearest as the kernels would round it on
+// load.
+static_assert(GBR_SLOT_FACE_UNHAT(2, 2, 2) == 38 && GBR_SLOT_CELL_UNHAT(0, 0) == 39 &&
+                  GBR_SLOT_CELL_UNHAT(2, 2) == kFloatMetricSlots - 1,
+              "float metric slots are the first 48");
+
+__global__ void __launch_bounds__(kBlock) k_metrics_float(const double *m, float *mf, long n)
+{
+    const long idx = blockIdx.x * (long)kBlock + threadIdx.x;
+    if (idx < n) mf[idx] = float(m[idx]);
+}
+
 }  // namespace
+
+hipError_t launch_metrics_float(gbr_grid_s *g)
+{
+    if (!g->metrics_f) return hipSuccess;
+    const long N = g->ncell;
+    const long n = N * kFloatMetricSlots;
+    hipLaunchKernelGGL(k_metrics_float, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, g->stream,
+                       (const double *)g->metrics, g->metrics_f, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
 {
@@ -511,7 +535,8 @@ hipError_t launch_metrics(gbr_grid_s *g, const double *xyz, const double *xyz_t)
                                dim3(kBlock), 0, g->stream, a);
     }
     hipLaunchKernelGGL(k_gcl, dim3(blocks), dim3(kBlock), 0, g->stream, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_metrics_float(g);
 }
 
 hipError_t launch_metrics_nonfp(gbr_grid_s *g, const double *xyz)
@@ -537,7 +562,8 @@ hipError_t launch_metrics_nonfp(gbr_grid_s *g, const double *xyz)
     hipLaunchKernelGGL(k_coord_deriv_c4, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     hipLaunchKernelGGL(k_cell_metrics_nonfp, dim3(blocks), dim3(kBlock), 0, g->stream, a);
     hipLaunchKernelGGL(k_face_metrics_c4, dim3(blocks), dim3(kBlock), 0, g->stream, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_metrics_float(g);
 }
 
 }  // namespace gbr

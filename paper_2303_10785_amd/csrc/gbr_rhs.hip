@@ -30,6 +30,8 @@
 // accumulates in double.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "gbr_device.hpp"
 #include "gbr_internal.hpp"
 
@@ -65,6 +67,9 @@ struct RhsArgs {
     R *theta;      // ncell
     R *prim;       // 6 * ncell: rho, u, v, w, p, T
     const double *m;  // metrics (always double)
+    const R *mr;      // the metrics the flux kernels read in the compute type:
+                      // m itself (FP64), or its float copy (FP32-bulk: slots
+                      // 0 .. 47, the face slots and cell unhatted metrics)
     int *flags;
     // SSP-RK3 stage fused into the last sweep (gbr_step only)
     const double *Qin; // stage input state
@@ -134,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
 // (div^2 + |curl|^2 + 1e-30) of the physical velocity gradient
 // G[a][b] = sum_d (d_{x_b}) du_a/dd from the computational gradients gd[d][a].
 template <class R>
-__device__ __forceinline__ void load_unhat(const double *m, long N, long idx, R mt[3][3])
+__device__ __forceinline__ void load_unhat(const R *m, long N, long idx, R mt[3][3])
 {
 #pragma unroll
     for (int b = 0; b < 3; ++b)
@@ -431,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) gd[d][q] = (d < NDIM) ? a.grad[(d * 4 + q) * N + idx] : R(0);
     R mt[3][3];
-    load_unhat(a.m, N, idx, mt);
+    load_unhat(a.mr, N, idx, mt);
     a.theta[idx] = ducros_theta(gd, mt);
 }
 
@@ -491,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
         // the sensor's metrics are requested before the halo loads and the
         // barrier, so their latency overlaps that work
         R mt[3][3];
-        if (SENSOR) load_unhat(a.m, N, pack(dm, ic, jc, k), mt);
+        if (SENSOR) load_unhat(a.mr, N, pack(dm, ic, jc, k), mt);
         if (NDIM == 3) {
             const long c = pack(dm, ic, jc, wrap_if(edge_k, k + 3, nk));
 #pragma unroll
@@ -700,7 +705,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const R *Pa = sP + T::at(t + 5, cl, NP);
     const R *Ga = s1 + T::at(t + 2, cl, N1);
     const R *Ha = s2 + T::at(t + 1, cl, N2);
-    const double *m = a.m;
+    const R *m = a.mr;
     if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     // In the eta and zeta sweeps the interface metrics are requested before
     // the unlimited states are formed, so their latency overlaps that work
@@ -1267,6 +1272,10 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.theta = reinterpret_cast<R *>(g->theta);
     a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;
+    if constexpr (std::is_same<R, float>::value)
+        a.mr = g->metrics_f;
+    else
+        a.mr = g->metrics;
     a.flags = g->flags;
     a.Qin = nullptr;
     a.Qout = nullptr;
