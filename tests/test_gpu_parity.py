@@ -346,6 +346,28 @@ def test_fp32_bulk_rhs_within_bound(gbr, case):
     assert e <= FP32_RHS_TOL
 
 
+def test_fp32_bulk_rhs_after_metric_update(gbr):
+    """FP32-bulk flux kernels read a float copy of the metrics: after a second
+    metric evaluation (a deforming grid at a later time) the RHS must use the
+    new metrics. Compared with the FP64 oracle at the second time."""
+    mv = W.Deforming3D((16, 14, 12), A=0.75, nmode=2, rand=0.2, seed=8)
+    params = dict(viscous=True, limiter="mp", Re=1e4, Mref=0.5)
+    g0, g1 = mv.at(0.0), mv.at(0.23)
+    Q = W.random_smooth_state(g1, seed=9)
+    h = gbr.Grid(g0, precision="fp32_bulk", **params)
+    h.metrics(dev(g0["xyz"]), dev(g0["xyz_t"]))
+    h.metrics(dev(g1["xyz"]), dev(g1["xyz_t"]))
+    Qd = dev(Q)
+    res = torch.empty(Qd.shape, dtype=torch.float32, device="cuda")
+    h.rhs(Qd, res)
+    torch.cuda.synchronize()
+    h.close()
+    ref = oracle.rhs(g1, oracle.metrics(g1, **params), Q, **params)
+    e = rel(res.double().cpu().numpy(), ref)
+    say(f"[fp32 rhs] after a metric update, max rel err vs FP64 oracle {e:.3e}")
+    assert e <= FP32_RHS_TOL
+
+
 def test_fp32_bulk_steps_config1(gbr):
     g = GRIDS["wavy2d_64"]()
     Q = W.shu_vortex(g, eps=5.0, xc=5.0, yc=5.0)
