@@ -144,6 +144,9 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
     static_assert(4 * (FX + FY) <= 4 * (VPX + VPY), "fluxes alias the pencils");
     __shared__ R sP[4 * (VPX + VPY)];  // xi pencils [v][y][x], then eta pencils [v][y][x]
     __shared__ R sG[4 * (VGX + VGY)];
+    // periodic indices of the cells i0-6 .. i0+TX+5 and j0-6 .. j0+TY+5, formed
+    // once per tile (one modulo each) for every phase of the tile
+    __shared__ int s_wi[TX + 12], s_wj[TY + 12];
     R *Px = sP, *Py = sP + 4 * VPX;
     R *Gx = sG, *Gy = sG + 4 * VGX;
     R *Fx = sP, *Fy = sP + 4 * FX;  // fluxes, after the pencils are consumed
@@ -160,6 +163,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
         const double *in = stage == 0 ? G.Q : (stage == 1 ? G.S1 : G.S2);
         double *out = stage == 0 ? G.S1 : (stage == 1 ? G.S2 : G.Q);
 
+        for (int q = tid; q < TX + 12; q += kBlock) s_wi[q] = wrap_index(i0 - 6 + q, ni);
+        for (int q = tid; q < TY + 12; q += kBlock) s_wj[q] = wrap_index(j0 - 6 + q, nj);
+        __syncthreads();
+        auto wi = [&](int i) { return s_wi[i - i0 + 6]; };  // i0-6 <= i < i0+TX+6
+        auto wj = [&](int j) { return s_wj[j - j0 + 6]; };
         auto prim = [&](long c, R *dst, int vs) {
             double r = in[c];
             double ir = 1.0 / r;  // as the single-grid primitives kernel
@@ -176,11 +184,11 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
         // i0+TX+5) and the eta pencils (columns i0.., cells j0-6 .. j0+TY+5)
         for (int e = tid; e < VPX; e += kBlock) {
             const int x = e % PXS, y = e / PXS;
-            prim(wrap_index(i0 - 6 + x, ni) + (long)ni * wrap_index(j0 + y, nj), Px + e, VPX);
+            prim(wi(i0 - 6 + x) + (long)ni * wj(j0 + y), Px + e, VPX);
         }
         for (int e = tid; e < VPY; e += kBlock) {
             const int x = e % TX, y = e / TX;
-            prim(wrap_index(i0 + x, ni) + (long)ni * wrap_index(j0 - 6 + y, nj), Py + e, VPY);
+            prim(wi(i0 + x) + (long)ni * wj(j0 - 6 + y), Py + e, VPY);
         }
         __syncthreads();
         // Phase 2: E6 first derivatives of cells i0-3 .. i0+TX+2 (xi) and
@@ -215,8 +223,8 @@ __global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, 
             const int fi = xi ? f % (TX + 1) : (f - FX) % TX;
             const int fj = xi ? f / (TX + 1) : (f - FX) / TX;
             // left cell of the face and its position in the pencils
-            const int ia = xi ? wrap_index(i0 + fi - 1, ni) : wrap_index(i0 + fi, ni);
-            const int ja = xi ? wrap_index(j0 + fj, nj) : wrap_index(j0 + fj - 1, nj);
+            const int ia = xi ? wi(i0 + fi - 1) : wi(i0 + fi);
+            const int ja = xi ? wj(j0 + fj) : wj(j0 + fj - 1);
             const long ca = ia + (long)ni * ja;
             const R *P = xi ? Px + fj * PXS + fi + 5 : Py + (fj + 5) * TX + fi;
             const R *Gd = xi ? Gx + fj * GXS + fi + 2 : Gy + (fj + 2) * TX + fi;
