@@ -20,6 +20,15 @@ __device__ __forceinline__ int wrap_index(int a, int n)
 // workgroup) skip the modulo.
 __device__ __forceinline__ int wrap_if(bool edge, int a, int n) { return edge ? wrap_index(a, n) : a; }
 
+// Division and square root in the compute type of the flux kernels:
+// correctly rounded in double; in float (the FP32-bulk path) the hardware
+// reciprocal and square root, within about one unit in the last place,
+// far inside that path's error bound.
+__device__ __forceinline__ double cdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float cdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double csqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float csqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Number of periods crossed going from [0, n) to index a (floor(a / n)).
 __device__ __forceinline__ int wrap_count(int a, int n)
 {
@@ -122,7 +131,7 @@ __device__ __forceinline__ R mp_limit(R wm1, R w0, R wp1, R dm1, R d0, R dp1, R 
 template <class R>
 __device__ __forceinline__ R viscosity(R T, R suth, R re)
 {
-    return T * sqrt(T) * (R(1) + suth) / ((T + suth) * re);
+    return cdiv(T * csqrt(T) * (R(1) + suth), (T + suth) * re);
 }
 
 // Curvilinear HLLC flux of Sec. 5.1.1 for primitive states L, R and
@@ -138,15 +147,15 @@ __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R
                                      R igm1, R F[5])
 {
     R nn = nx * nx + ny * ny + nz * nz;
-    R sn = sqrt(nn);
+    R sn = csqrt(nn);
     R UL = nt + nx * PL[1] + ny * PL[2] + nz * PL[3];
     R UR = nt + nx * PR[1] + ny * PR[2] + nz * PR[3];
-    R cL = sqrt(gamma * PL[4] / PL[0]);
-    R cR = sqrt(gamma * PR[4] / PR[0]);
+    R cL = csqrt(cdiv(gamma * PL[4], PL[0]));
+    R cR = csqrt(cdiv(gamma * PR[4], PR[0]));
     R SL = fmin(UL - cL * sn, UR - cR * sn);
     R SR = fmax(UL + cL * sn, UR + cR * sn);
-    R Ss = (PR[0] * UR * (SR - UR) - PL[0] * UL * (SL - UL) + (PL[4] - PR[4]) * nn) /
-           (PR[0] * (SR - UR) - PL[0] * (SL - UL));
+    R Ss = cdiv(PR[0] * UR * (SR - UR) - PL[0] * UL * (SL - UL) + (PL[4] - PR[4]) * nn,
+                PR[0] * (SR - UR) - PL[0] * (SL - UL));
 
     bool useL = (R(0) <= SL) || (!(R(0) >= SR) && (R(0) <= Ss));
     bool star = !(R(0) <= SL) && !(R(0) >= SR);
@@ -161,8 +170,8 @@ __device__ __forceinline__ void hllc(const R PL[5], const R PR[5], R nt, R nx, R
     F[3] = r * w * U + nz * p;
     F[4] = (E + p) * U - nt * p;
     if (star) {
-        const R inn = R(1) / nn;
-        const R isk = R(1) / (SK - Ss);
+        const R inn = cdiv(R(1), nn);
+        const R isk = cdiv(R(1), SK - Ss);
         const R d = SK - U;
         const R fac = r * d * isk;
         const R fn = fac * inn;
@@ -251,9 +260,9 @@ __device__ __forceinline__ void limited_states(const R *P, const R *G, int ST, i
     const int ip = (NVL == 4) ? 3 : 4;
     R rb = R(0.5) * (P[0] + P[ST]);
     R pb = R(0.5) * (P[ip * vsP] + P[ip * vsP + ST]);
-    R ab2 = gamma * pb / rb;
-    R ra = rb * sqrt(ab2);
-    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
+    R ab2 = cdiv(gamma * pb, rb);
+    R ra = rb * csqrt(ab2);
+    R inn = cdiv(R(1), csqrt(nx * nx + ny * ny + nz * nz));
     R ex = nx * inn, ey = ny * inn, ez = nz * inn;
     // projection of a primitive vector x:
     //   W0 = p - ra (e.u),  W4 = p + ra (e.u),
@@ -306,8 +315,8 @@ __device__ __forceinline__ void limited_states(const R *P, const R *G, int ST, i
         WR[v] = mp_limit(W[3][v], W[2][v], W[1][v], W2[3][v], W2[2][v], W2[1][v], wr, alpha_mp, beta_mp);
     }
     // right eigenvectors (App. A)
-    R ia2 = R(1) / ab2;
-    R i2ra = R(0.5) / ra;
+    R ia2 = cdiv(R(1), ab2);
+    R i2ra = cdiv(R(0.5), ra);
     auto back = [&](const R *w, R *x) {
         R h = (w[4] - w[0]) * i2ra;
         x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;
@@ -358,9 +367,9 @@ __device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const
     const int ip = (NVL == 4) ? 3 : 4;
     R rb = R(0.5) * (P[0] + P[ST]);
     R pb = R(0.5) * (P[ip * vsP] + P[ip * vsP + ST]);
-    R ab2 = gamma * pb / rb;
-    R ra = rb * sqrt(ab2);
-    R inn = R(1) / sqrt(nx * nx + ny * ny + nz * nz);
+    R ab2 = cdiv(gamma * pb, rb);
+    R ra = rb * csqrt(ab2);
+    R inn = cdiv(R(1), csqrt(nx * nx + ny * ny + nz * nz));
     R ex = nx * inn, ey = ny * inn, ez = nz * inn;
     auto ld = [&](const R *x, int vs, int v, int o) { return pencil<NVL>(x, vs, v, o); };
     // point k = 0..3: cells a-1 .. a+2 (values and curvatures), k = 0..1:
@@ -413,8 +422,8 @@ __device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const
         limit(v, w, d, g);
     }
     // right eigenvectors (App. A)
-    R ia2 = R(1) / ab2;
-    R i2ra = R(0.5) / ra;
+    R ia2 = cdiv(R(1), ab2);
+    R i2ra = cdiv(R(0.5), ra);
     auto back = [&](const R *w, R *x) {
         R h = (w[4] - w[0]) * i2ra;
         x[0] = (R(0.5) * (w[0] + w[4]) + ex * w[1] + ez * w[2] - ey * w[3]) * ia2;

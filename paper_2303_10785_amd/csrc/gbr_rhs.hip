@@ -159,7 +159,7 @@ __device__ __forceinline__ R ducros_theta(const R gd[3][4], const R mt[3][3])
     R div = G[0][0] + G[1][1] + G[2][2];
     R wx = G[2][1] - G[1][2], wy = G[0][2] - G[2][0], wz = G[1][0] - G[0][1];
     R d2 = div * div;
-    return d2 / (d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
+    return cdiv(d2, d2 + (wx * wx + wy * wy + wz * wz) + R(1e-30));
 }
 
 // MIG4 gradients (Eq. IG4_grads, read as differences, alpha = 5/14) from the
