@@ -236,9 +236,9 @@ __global__ void __launch_bounds__(kBlock) k_face_metrics(MetricArgs a, Ig4Metric
             for (int q = -4; q <= 5; ++q) nb[q + 4] = neighbour(a.dm, ijk, f, q, idx, 5, nullptr);
         auto interp = [&](int slot) {
             const double *s = m + slot * N;
-            return interface<IG4>(st, [&](int q) {
-                return IG4 ? s[neighbour(a.dm, ijk, f, q, idx, kIg4Half + 2, nullptr)] : s[nb[q + 4]];
-            });
+            // (the 100-point IG4 window keeps step_to: a per-point choice
+            // inside that loop cost more than the modulos it saves)
+            return interface<IG4>(st, [&](int q) { return IG4 ? s[step_to(a.dm, ijk, f, q, nullptr)] : s[nb[q + 4]]; });
         };
         for (int c = 0; c < 3; ++c) m[GBR_SLOT_FACE_HAT(f, c) * N + idx] = interp(GBR_SLOT_CELL_HAT(f, c));
         m[GBR_SLOT_FACE_HATT(f) * N + idx] = interp(GBR_SLOT_CELL_HATT(f));
