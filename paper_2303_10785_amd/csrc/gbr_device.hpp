@@ -358,15 +358,15 @@ __device__ __forceinline__ void direct_states(const R *P, const R *G, int ST, in
 // indexing as P). The characteristic fields are formed and limited in small
 // groups straight from the pencils, (W0, W4) together and W1, W2, W3 one at
 // a time, so few projected values are live at once.
-template <int NVL, class R>
-__device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const R *H, int ST, int vsP, int vsG,
+template <int NVL, bool REREAD, class R>
+__device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, const R *H0, int ST, int vsP, int vsG,
                                                    int vsH, R nx, R ny, R nz, R gamma, R alpha_mp, R beta_mp,
                                                    R PL[5], R PR[5])
 {
     const R twelfth = R(1.0 / 12.0);
     const int ip = (NVL == 4) ? 3 : 4;
-    R rb = R(0.5) * (P[0] + P[ST]);
-    R pb = R(0.5) * (P[ip * vsP] + P[ip * vsP + ST]);
+    R rb = R(0.5) * (P0[0] + P0[ST]);
+    R pb = R(0.5) * (P0[ip * vsP] + P0[ip * vsP + ST]);
     R ab2 = cdiv(gamma * pb, rb);
     R ra = rb * csqrt(ab2);
     R inn = cdiv(R(1), csqrt(nx * nx + ny * ny + nz * nz));
@@ -382,10 +382,18 @@ __device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const
         WR[v] = mp_limit(w[3], w[2], w[1], d[3], d[2], d[1], wr, alpha_mp, beta_mp);
     };
     // W0 = p - ra (e.u), W4 = p + ra (e.u), one field at a time (fewer live
-    // registers at the limiter's peak; the pencils are read twice from LDS)
+    // registers at the limiter's peak). With REREAD each field reads the
+    // pencils from LDS again: an opaque zero offset keeps the compiler from
+    // merging the reads of the five fields and holding every pencil value
+    // across all of them (FP64 xi sweep 148 -> 106 VGPRs, a fourth wave per
+    // SIMD; the eta / zeta sweeps, held at three by their LDS, only pay the
+    // extra reads and keep the merged form).
 #pragma unroll
     for (int sgn = -1; sgn <= 1; sgn += 2) {
         R w[4], d[4], g[2];
+        int z = 0;
+        if (REREAD) __asm__ volatile("" : "+v"(z));
+        const R *P = P0 + z, *G = G0 + z, *H = H0 + z;
         auto acoustic = [&](const R *x, int vs, int o) {
             R un = ex * ld(x, vs, 1, o) + ey * ld(x, vs, 2, o) + ez * ld(x, vs, 3, o);
             R x4 = ld(x, vs, 4, o);
@@ -412,6 +420,9 @@ __device__ __forceinline__ void limited_states_pre(const R *P, const R *G, const
 #pragma unroll
     for (int v = 1; v <= 3; ++v) {
         R w[4], d[4], g[2];
+        int z = 0;
+        if (REREAD) __asm__ volatile("" : "+v"(z));
+        const R *P = P0 + z, *G = G0 + z, *H = H0 + z;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             w[k] = entropy_shear(v, P, vsP, (k - 1) * ST);

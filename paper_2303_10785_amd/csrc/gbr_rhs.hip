@@ -730,7 +730,8 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
             R lx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
             R ly = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
             R lz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
-            limited_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, lx, ly, lz, ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
+            limited_states_pre<5, D == 0 && sizeof(R) == 8>(Pa, Ga, Ha, st, VP, V1, V2, lx, ly, lz, ph.gamma,
+                                                             ph.alpha_mp, ph.beta_mp, PL, PR);
         }
         if (pre) load_face();
     } else {
