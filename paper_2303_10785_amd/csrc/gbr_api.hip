@@ -152,8 +152,8 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->metrics_f, (void *)g->scratch, (void *)g->theta, (void *)g->grad2, (void *)g->prim,
-                    (void *)g->prim2, (void *)g->sigma,
+    for (void *p : {(void *)g->metrics, (void *)g->metrics_f, (void *)g->scratch, (void *)g->theta,
+                    (void *)g->grad2, (void *)g->prim, (void *)g->prim2, (void *)g->sigma,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
         if (p) (void)hipFree(p);
@@ -255,7 +255,8 @@ gbr_status gbr_metrics(const gbr_grid *g, int n, const double *const *xyz, const
         const double *xt = xyz_t ? xyz_t[b] : nullptr;
         if (gg->cfg.moving && !xt) return fail(gg, GBR_E_ARG, "moving grid needs grid velocities");
         hipError_t e = hipMemsetAsync(gg->flags + 1, 0, sizeof(int), gg->stream);
-        if (e == hipSuccess) e = gg->bounded ? gbr::launch_metrics_bounded(gg, xyz[b]) : gbr::launch_metrics(gg, xyz[b], xt);
+        if (e == hipSuccess)
+            e = gg->bounded ? gbr::launch_metrics_bounded(gg, xyz[b]) : gbr::launch_metrics(gg, xyz[b], xt);
         if (e != hipSuccess) return hip_fail(gg, e, "metrics launch");
     }
     for (int b = 0; b < n; ++b) {

@@ -355,9 +355,9 @@ __device__ __forceinline__ void direct_states(const R *P, const R *G, int ST, in
 
 // Limited interface states as in limited_states, with the Hermite second
 // derivatives precomputed per cell (H, variable stride vsH, same cell
-// indexing as P). The characteristic fields are formed and limited in small
-// groups straight from the pencils, (W0, W4) together and W1, W2, W3 one at
-// a time, so few projected values are live at once.
+// indexing as P). The characteristic fields are formed and limited one at
+// a time straight from the pencils, so few projected values are live at
+// once.
 template <int NVL, bool REREAD, class R>
 __device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, const R *H0, int ST, int vsP, int vsG,
                                                    int vsH, R nx, R ny, R nz, R gamma, R alpha_mp, R beta_mp,

@@ -29,7 +29,6 @@
 // float, while Q, the metrics, J and (1/J)_t stay in double and the RK stage
 // accumulates in double.
 #include <algorithm>
-
 #include <type_traits>
 
 #include "gbr_device.hpp"
