@@ -55,7 +55,9 @@ enum { GBR_LIM_NONE = 0, GBR_LIM_MP = 1, GBR_LIM_DUCROS = 2 };
 /* Precision: GBR_FP64 computes everything in double. GBR_FP32_BULK keeps Q,
  * the metrics, J, (1/J)_t, the time step and the RK accumulation in double
  * and runs primitives, gradients, the sensor, reconstruction, limiter, HLLC,
- * viscous flux and Res in float.                                            */
+ * viscous flux and Res in float; those float kernels read the metrics from
+ * a float copy rounded once after each gbr_metrics call, and divide and take
+ * square roots with the hardware reciprocal and square root (about 1 ulp). */
 enum { GBR_FP64 = 0, GBR_FP32_BULK = 1 };
 enum { GBR_DT_CFL = 0, GBR_DT_FIXED = 1 };
 /* Gradient scheme of Sec. 5.1 Step-1: GBR_SCHEME_MEG6 uses the explicit
