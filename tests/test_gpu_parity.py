@@ -158,6 +158,34 @@ def test_rhs_is_deterministic(gbr):
     assert torch.equal(r1, r2)
 
 
+@pytest.mark.parametrize("precision,scheme", [("fp64", "meg6"), ("fp32_bulk", "meg6"), ("fp64", "mig4")])
+def test_steps_are_deterministic(gbr, precision, scheme):
+    """Two grid handles stepped alike give bitwise-equal states and time
+    steps: every reduction (the time-step minimum, the sensor gather) is
+    order-independent. Multi-tile lines along xi (130 cells: two 63-cell
+    tiles and a tail tile) and the Ducros-gated limiter."""
+    g = W.jet3d((130, 40, 36))
+    Q = W.jet_ic(g)
+    params = dict(viscous=True, limiter="ducros", Re=1.144e6, precision=precision, scheme=scheme)
+    say(f"[determinism] jet 130x40x36 {precision} {scheme}, 5 steps")
+    out = []
+    for _ in range(2):
+        h = gbr.Grid(g, **params)
+        h.metrics(dev(g["xyz"]))
+        Qd = dev(Q)
+        dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dts = []
+        for _ in range(5):
+            h.step(Qd, 0.2, gbr.GBR_DT_CFL, dt_out=dt)
+            dts.append(dt.clone())
+        torch.cuda.synchronize()
+        assert h.check_state() == gbr.GBR_OK
+        h.close()
+        out.append((Qd, torch.cat(dts)))
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
+
+
 def test_step_parity_config1_vortex(gbr):
     """2-D Euler isentropic vortex (strength 5) on the periodic 64x64 wavy
     grid, gradient-based reconstruction + MP + HLLC, SSP-RK3 at CFL 0.4,
