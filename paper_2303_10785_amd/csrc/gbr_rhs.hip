@@ -42,7 +42,7 @@ constexpr int kBlock = 256;
 #define GBR_TS_CROSS 16
 #endif
 #ifndef GBR_TS_XI
-#define GBR_TS_XI 64
+#define GBR_TS_XI 128
 #endif
 #ifndef GBR_COMPACT_DIRS
 #define GBR_COMPACT_DIRS 7  // bit D: gather the sensor-flagged interfaces of sweep D (FP64)
@@ -1055,11 +1055,11 @@ void launch_sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode, int tiles_s, int
                            main_blocks, s_tail);
 }
 
-// xi lines are cut into tiles of GBR_TS_XI - 1 = 63 cells; a remainder of
+// xi lines are cut into tiles of GBR_TS_XI - 1 = 127 cells; a remainder of
 // fewer than GBR_TS_XI_TAIL cells goes to one narrow tile per line
 // (GBR_TS_XI_TAIL faces, kBlock / GBR_TS_XI_TAIL lines per workgroup) in the
-// same launch, so that few lanes idle (a 400-cell line: 6 tiles and 22 cells
-// in a 32-face tile, instead of 7 tiles with 41 idle lanes).
+// same launch, so that few lanes idle (a 400-cell line: 3 tiles and 19 cells
+// in a 32-face tile, instead of 4 tiles with 108 idle lanes).
 #ifndef GBR_TS_XI_TAIL
 #define GBR_TS_XI_TAIL 32
 #endif
@@ -1084,7 +1084,7 @@ hipError_t sweep(gbr_grid_s *g, const RhsArgs<R> &a, int mode)
 // first writes Res, the others add to it, and with fuse_rk the xi sweep
 // applies the SSP-RK3 stage. The stage's extra traffic (Q, Qn, J, (1/J)_t
 // in, Q and the next primitives out) coalesces best in the xi tiles, whose
-// rows are 64 cells (512 bytes) long against 16 in the eta / zeta tiles.
+// rows are 128 cells (1 KiB) long against 16 in the eta / zeta tiles.
 template <int NDIM, bool VISC, class R, bool IG4>
 hipError_t sweeps(gbr_grid_s *g, const RhsArgs<R> &a, bool fuse_rk)
 {

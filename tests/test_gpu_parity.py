@@ -436,12 +436,12 @@ def test_fp32_bulk_freestream_moving(gbr):
     assert vmax < 1e-5
 
 
-# xi line lengths around the sweep's tiling: lines are cut into 63-cell
+# xi line lengths around the sweep's tiling: lines are cut into 127-cell
 # tiles and a remainder below 32 cells goes to a 32-face tail tile in the
-# same launch. 31: tail only; 32: one partial full tile; 63: one exact tile;
-# 64: a tile and a 1-cell tail; 94: a tile and the largest tail (31);
-# 95: two tiles, the second partial; 126: two exact tiles.
-XI_LENGTHS = [31, 32, 63, 64, 94, 95, 126]
+# same launch. 31: tail only; 32, 64: one partial full tile; 127: one exact
+# tile; 128: a tile and a 1-cell tail; 158: a tile and the largest tail (31);
+# 159: two tiles, the second partial; 254: two exact tiles.
+XI_LENGTHS = [31, 32, 64, 127, 128, 158, 159, 254]
 
 
 @pytest.mark.parametrize("ni", XI_LENGTHS)
