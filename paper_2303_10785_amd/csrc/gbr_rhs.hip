@@ -48,6 +48,30 @@ constexpr int kBlock = 256;
 #define GBR_COMPACT_DIRS 7  // bit D: gather the sensor-flagged interfaces of sweep D (FP64)
 #endif
 
+// Workgroups are handed to the eight XCDs in turn, and each XCD has its own
+// L2. Neighbouring tiles of a line share halo cells, and with them whole
+// 128-byte lines; in launch order they land on different XCDs, whose L2s
+// each fetch those lines. The tiled kernels therefore take their tile from
+// a permuted block index: within each run of 8 x GBR_XCD_GROUP consecutive
+// blocks, block 8a + x (on XCD x) takes tile GBR_XCD_GROUP x + a, so
+// GBR_XCD_GROUP consecutive tiles run on one XCD at about the same time and
+// the shared lines are fetched once into its L2. The order across the grid
+// is unchanged, and blocks past the last full run keep their own tile.
+// (On the 13 M jet: FP64 sweeps and gradients read 149 B per cell-RHS less;
+// FP32-bulk step 7.4 -> 6.85 ms, FP64 11.2 -> 11.1 ms.)
+#ifndef GBR_XCD_GROUP
+#define GBR_XCD_GROUP 8
+#endif
+__device__ __forceinline__ void tile_of_block(int &bx, int &by)
+{
+    constexpr unsigned run = 8u * GBR_XCD_GROUP;
+    const unsigned nx = gridDim.x, total = nx * gridDim.y;
+    unsigned b = blockIdx.x + nx * blockIdx.y;
+    if (b / run < total / run) b = run * (b / run) + GBR_XCD_GROUP * (b % 8u) + (b % run) / 8u;
+    bx = int(b % nx);
+    by = int(b / nx);
+}
+
 template <class R>
 struct PhysR {
     R gamma, igm1, gM2, suth, re, ikden, theta_c, alpha_mp, beta_mp, alpha_d;  // igm1 = 1 / gm1, ikden = 1 / kden
@@ -238,9 +262,10 @@ __global__ void __launch_bounds__(kBlock) k_ig4_rec(RhsArgs<R> a, Ig4Rec rc)
     const long N = dm.ncell;
     const int ns = dm.n[T::SD], nc = dm.n[T::CD];
     const int tiles_s = (ns + TS - 1) / TS;
-    const int s0 = (blockIdx.x % tiles_s) * TS;
-    const int c0 = (blockIdx.x / tiles_s) * TC;
-    const int o = blockIdx.y;
+    int bx, o;
+    tile_of_block(bx, o);
+    const int s0 = (bx % tiles_s) * TS;
+    const int c0 = (bx / tiles_s) * TC;
     const int tid = threadIdx.x;
     const int cl = T::line_of(tid), sg = T::seg_of(tid);
     const int p0 = sg * S;  // first position of this thread's segment
@@ -471,8 +496,10 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
     const long N = dm.ncell;
     const int ni = dm.n[0], nj = dm.n[1], nk = dm.n[2];
     const int tiles_i = (ni + GI - 1) / GI;
-    const int i0 = (blockIdx.x % tiles_i) * GI, j0 = (blockIdx.x / tiles_i) * GJ;
-    const int k0 = blockIdx.y * KC;
+    int bx, bz;
+    tile_of_block(bx, bz);
+    const int i0 = (bx % tiles_i) * GI, j0 = (bx / tiles_i) * GJ;
+    const int k0 = bz * KC;
     const int ti = threadIdx.x % GI, tj = threadIdx.x / GI;
     const int i = i0 + ti, j = j0 + tj;
     const bool inside = i < ni && j < nj;
@@ -583,7 +610,7 @@ struct Tile {
 // line, the first starting at cell s_begin. The LDS arrays come from the
 // kernel, sized for the largest tile shape it runs.
 template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R, int TSO>
-__device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int tiles_s, int bx, R *sP, R *s1,
+__device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int tiles_s, int bx, int o, R *sP, R *s1,
                                            R *s2, int *s_order, int *s_count)
 {
     using T = Tile<D, TSO>;
@@ -598,7 +625,6 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const int tcb = bx / tiles_s;
     const int s0 = s_begin + ts * (TS - 1);
     const int c0 = tcb * TC;
-    const int o = blockIdx.y;
     const int tid = threadIdx.x;
     // every cell this tile touches along D (s0 - 6 .. s0 + TS + 4) lies in
     // [0, ns) unless the tile sits at an end of its line
@@ -903,10 +929,11 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
 
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
 
-// A sweep launch: blocks [0, main_blocks) are tiles of the default shape,
-// tiles_s per line starting at cell 0; with TAIL > 0 the remaining blocks are
-// one TAIL-face tile per line starting at cell s_tail (the remainder of each
-// line), dispatched after the others so they fill the launch's drain.
+// A sweep launch: in each row of the grid (one outer index), tiles
+// [0, main_blocks) have the default shape, tiles_s per line starting at
+// cell 0; with TAIL > 0 the remaining tiles of the row are one TAIL-face
+// tile per line starting at cell s_tail (the remainder of each line), so
+// the narrow tiles run in the same launch as the full ones.
 template <int D, int NDIM, bool VISC, int MODE, bool IG4, class R, int TAIL>
 __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a, int tiles_s, int main_blocks, int s_tail)
 {
@@ -917,10 +944,12 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a, int tiles_s, int main_blo
     __shared__ R s2[5 * cmax(T0::N2 * T0::TC, T1::N2 * T1::TC)];
     __shared__ int s_order[kBlock];
     __shared__ int s_count[kBlock / 64];
-    if (TAIL == 0 || (int)blockIdx.x < main_blocks)
-        sweep_tile<D, NDIM, VISC, MODE, IG4, R, 0>(a, 0, tiles_s, blockIdx.x, sP, s1, s2, s_order, s_count);
+    int bx, o;
+    tile_of_block(bx, o);
+    if (TAIL == 0 || bx < main_blocks)
+        sweep_tile<D, NDIM, VISC, MODE, IG4, R, 0>(a, 0, tiles_s, bx, o, sP, s1, s2, s_order, s_count);
     else
-        sweep_tile<D, NDIM, VISC, MODE, IG4, R, TAIL>(a, s_tail, 1, blockIdx.x - main_blocks, sP, s1, s2, s_order,
+        sweep_tile<D, NDIM, VISC, MODE, IG4, R, TAIL>(a, s_tail, 1, bx - main_blocks, o, sP, s1, s2, s_order,
                                                       s_count);
 }
 
