@@ -57,10 +57,12 @@ constexpr int kBlock = 256;
 // GBR_XCD_GROUP consecutive tiles run on one XCD at about the same time and
 // the shared lines are fetched once into its L2. The order across the grid
 // is unchanged, and blocks past the last full run keep their own tile.
-// (On the 13 M jet: FP64 sweeps and gradients read 149 B per cell-RHS less;
-// FP32-bulk step 7.4 -> 6.85 ms, FP64 11.2 -> 11.1 ms.)
+// Groups of 32 also hold the neighbours across the lines of a tile in the
+// eta / zeta sweeps, whose FP32 rows (16 floats) are half a 128-byte line.
+// (On the 13 M jet: FP64 sweeps and gradients read about 150 B per
+// cell-RHS less; FP32-bulk step 7.4 -> 6.55 ms, FP64 11.2 -> 11.1 ms.)
 #ifndef GBR_XCD_GROUP
-#define GBR_XCD_GROUP 8
+#define GBR_XCD_GROUP 32
 #endif
 __device__ __forceinline__ void tile_of_block(int &bx, int &by)
 {
