@@ -354,11 +354,13 @@ __device__ __forceinline__ void direct_states(const R *P, const R *G, int ST, in
 }
 
 // Limited interface states as in limited_states, with the Hermite second
-// derivatives precomputed per cell (H, variable stride vsH, same cell
-// indexing as P). The characteristic fields are formed and limited one at
-// a time straight from the pencils, so few projected values are live at
+// derivatives precomputed per cell (CURV: H, variable stride vsH, same cell
+// indexing as P) or formed per characteristic field from its values and
+// first derivatives (not CURV: P and G are read at cells a-2 .. a+3, H is
+// not read). The characteristic fields are formed and limited one at a
+// time straight from the pencils, so few projected values are live at
 // once.
-template <int NVL, bool REREAD, class R>
+template <int NVL, bool REREAD, bool CURV = true, class R>
 __device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, const R *H0, int ST, int vsP, int vsG,
                                                    int vsH, R nx, R ny, R nz, R gamma, R alpha_mp, R beta_mp,
                                                    R PL[5], R PR[5])
@@ -381,13 +383,44 @@ __device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, con
         WL[v] = mp_limit(w[0], w[1], w[2], d[0], d[1], d[2], wl, alpha_mp, beta_mp);
         WR[v] = mp_limit(w[3], w[2], w[1], d[3], d[2], d[1], wr, alpha_mp, beta_mp);
     };
+    // one field's values w and curvatures d at cells a-1 .. a+2 and first
+    // derivatives g at a, a+1, through its projection F(pencil, stride,
+    // offset). Without CURV the curvatures are formed from the field's
+    // values and first derivatives at a-2 .. a+3 (the Hermite formula is
+    // linear, so this equals projecting the primitive curvatures up to
+    // rounding).
+    auto field = [&](auto F, const R *P, const R *G, const R *H, R w[4], R d[4], R g[2]) {
+        if constexpr (CURV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = F(P, vsP, (k - 1) * ST);
+                d[k] = F(H, vsH, (k - 1) * ST);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) g[k] = F(G, vsG, k * ST);
+        } else {
+            R w6[6], g6[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                w6[k] = F(P, vsP, (k - 2) * ST);
+                g6[k] = F(G, vsG, (k - 2) * ST);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                w[k] = w6[k + 1];
+                d[k] = hermite2(w6[k], w6[k + 1], w6[k + 2], g6[k], g6[k + 2]);
+            }
+            g[0] = g6[2];
+            g[1] = g6[3];
+        }
+    };
     // W0 = p - ra (e.u), W4 = p + ra (e.u), one field at a time (fewer live
     // registers at the limiter's peak). With REREAD each field reads the
     // pencils from LDS again: an opaque zero offset keeps the compiler from
     // merging the reads of the five fields and holding every pencil value
-    // across all of them (FP64 xi sweep 148 -> 106 VGPRs, a fourth wave per
-    // SIMD; the eta / zeta sweeps, held at three by their LDS, only pay the
-    // extra reads and keep the merged form).
+    // across all of them (FP64 sweeps: xi 148 -> 106 VGPRs, eta / zeta
+    // without the curvature array 168 with spills -> 108, a fourth wave per
+    // SIMD).
 #pragma unroll
     for (int sgn = -1; sgn <= 1; sgn += 2) {
         R w[4], d[4], g[2];
@@ -399,13 +432,7 @@ __device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, con
             R x4 = ld(x, vs, 4, o);
             return sgn < 0 ? x4 - ra * un : x4 + ra * un;
         };
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            w[k] = acoustic(P, vsP, (k - 1) * ST);
-            d[k] = acoustic(H, vsH, (k - 1) * ST);
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) g[k] = acoustic(G, vsG, k * ST);
+        field(acoustic, P, G, H, w, d, g);
         limit(sgn < 0 ? 0 : 4, w, d, g);
     }
     // W1 = ex s + (ey w - ez v), W2 = ez s + (ex v - ey u),
@@ -423,13 +450,7 @@ __device__ __forceinline__ void limited_states_pre(const R *P0, const R *G0, con
         int z = 0;
         if (REREAD) __asm__ volatile("" : "+v"(z));
         const R *P = P0 + z, *G = G0 + z, *H = H0 + z;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            w[k] = entropy_shear(v, P, vsP, (k - 1) * ST);
-            d[k] = entropy_shear(v, H, vsH, (k - 1) * ST);
-        }
-#pragma unroll
-        for (int k = 0; k < 2; ++k) g[k] = entropy_shear(v, G, vsG, k * ST);
+        field([&](const R *x, int vs, int o) { return entropy_shear(v, x, vs, o); }, P, G, H, w, d, g);
         limit(v, w, d, g);
     }
     // right eigenvectors (App. A)

@@ -47,6 +47,17 @@ constexpr int kBlock = 256;
 #ifndef GBR_COMPACT_DIRS
 #define GBR_COMPACT_DIRS 7  // bit D: gather the sensor-flagged interfaces of sweep D (FP64)
 #endif
+// Where the sweep keeps the Hermite second derivatives of its cells in an
+// LDS array (formed once per cell) and where each interface forms the
+// curvatures of its characteristic fields from their values and first
+// derivatives instead (limited_states_pre). The FP64 eta / zeta sweeps do
+// the latter: without the array their LDS drops from 43.9 to 31.8 KB and,
+// with the limiter's per-field pencil reads, their registers from 162 to
+// 108, a fourth wave per SIMD (eta -3 %, MIG4 eta / zeta -5 / -2 % on the
+// 13 M jet). The FP64 xi sweep, already at four waves, and the FP32-bulk
+// sweeps keep the array: for them the extra arithmetic costs more.
+template <int D, class R>
+constexpr bool kCurvLds = sizeof(R) == 4 || D == 0;
 
 // Workgroups are handed to the eight XCDs in turn, and each XCD has its own
 // L2. Neighbouring tiles of a line share halo cells, and with them whole
@@ -671,21 +682,24 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         }
     }
     __syncthreads();
-    // Hermite second derivatives (Step-1) of cells s0-2 .. s0+TS, once per cell
-    for (int e = tid; e < V2; e += kBlock) {
-        int sl = (D == 0) ? e % N2 : e / TC;
-        int cl = (D == 0) ? e / N2 : e % TC;
-        int pc = T::at(sl + 4, cl, NP);
-        int gc = T::at(sl + 1, cl, N1);
-        int at = T::at(sl, cl, N2);
+    // Hermite second derivatives (Step-1) of cells s0-2 .. s0+TS, once per
+    // cell, where the sweep keeps them in LDS
+    if constexpr (kCurvLds<D, R>) {
+        for (int e = tid; e < V2; e += kBlock) {
+            int sl = (D == 0) ? e % N2 : e / TC;
+            int cl = (D == 0) ? e / N2 : e % TC;
+            int pc = T::at(sl + 4, cl, NP);
+            int gc = T::at(sl + 1, cl, N1);
+            int at = T::at(sl, cl, N2);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-            const R *x = sP + v * VP + pc;
-            const R *g = s1 + v * V1 + gc;
-            s2[v * V2 + at] = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
+            for (int v = 0; v < 5; ++v) {
+                const R *x = sP + v * VP + pc;
+                const R *g = s1 + v * V1 + gc;
+                s2[v * V2 + at] = hermite2(x[-st], x[0], x[st], g[-st], g[st]);
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // Phase 3: one interface per thread. Interface f (f = thread id of its
     // home lane) lies between cells a = s0+t-1 and a+1 with t = t_of(f).
@@ -731,7 +745,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const long cb = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t, ns), cgc, o);
     const R *Pa = sP + T::at(t + 5, cl, NP);
     const R *Ga = s1 + T::at(t + 2, cl, N1);
-    const R *Ha = s2 + T::at(t + 1, cl, N2);
+    const R *Ha = kCurvLds<D, R> ? s2 + T::at(t + 1, cl, N2) : Pa;
     const R *m = a.mr;
     if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
     // In the eta and zeta sweeps the interface metrics are requested before
@@ -757,13 +771,16 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
             R lx = R(m[GBR_SLOT_FACE_HAT(D, 0) * N + ca]);
             R ly = R(m[GBR_SLOT_FACE_HAT(D, 1) * N + ca]);
             R lz = (NDIM == 3) ? R(m[GBR_SLOT_FACE_HAT(D, 2) * N + ca]) : R(0);
-            limited_states_pre<5, D == 0 && sizeof(R) == 8>(Pa, Ga, Ha, st, VP, V1, V2, lx, ly, lz, ph.gamma,
-                                                             ph.alpha_mp, ph.beta_mp, PL, PR);
+            limited_states_pre<5, sizeof(R) == 8, kCurvLds<D, R>>(Pa, Ga, Ha, st, VP, V1, V2, lx, ly, lz,
+                                                                             ph.gamma, ph.alpha_mp, ph.beta_mp, PL, PR);
         }
         if (pre) load_face();
     } else {
         if (pre) load_face();
-        direct_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, PL, PR);
+        if constexpr (kCurvLds<D, R>)
+            direct_states_pre<5>(Pa, Ga, Ha, st, VP, V1, V2, PL, PR);
+        else
+            direct_states<5>(Pa, Ga, st, VP, V1, PL, PR);
     }
     if (!pre) load_face();
     if (NDIM == 2) {
@@ -943,7 +960,7 @@ __global__ void GBR_SWEEP_BOUNDS k_sweep(RhsArgs<R> a, int tiles_s, int main_blo
     using T1 = Tile<D, TAIL ? TAIL : T0::TS>;
     __shared__ R sP[5 * cmax(T0::NP * T0::TC, T1::NP * T1::TC)];
     __shared__ R s1[5 * cmax(T0::N1 * T0::TC, T1::N1 * T1::TC)];
-    __shared__ R s2[5 * cmax(T0::N2 * T0::TC, T1::N2 * T1::TC)];
+    __shared__ R s2[kCurvLds<D, R> ? 5 * cmax(T0::N2 * T0::TC, T1::N2 * T1::TC) : 1];
     __shared__ int s_order[kBlock];
     __shared__ int s_count[kBlock / 64];
     int bx, o;
