@@ -121,9 +121,17 @@ __device__ __forceinline__ bool face_flux_2d(const R *P, const R *G, int st, int
                                              R gamma, R igm1, R alpha_mp, R beta_mp, R phi[5])
 {
     R PL[5], PR[5];
-    if (LIM)
-        limited_states<4>(P, G, st, vsP, vsG, nx, ny, R(0), gamma, alpha_mp, beta_mp, PL, PR);
-    else
+    if (LIM) {
+        // FP64: one characteristic field at a time, its curvatures formed
+        // from its values and first derivatives (252 -> 168 VGPRs with the
+        // 16 x 16 tile, a third wave per SIMD); FP32 keeps all fields
+        // together, which its registers allow
+        if constexpr (sizeof(R) == 8)
+            limited_states_pre<4, true, false>(P, G, P, st, vsP, vsG, 0, nx, ny, R(0), gamma, alpha_mp, beta_mp, PL,
+                                               PR);
+        else
+            limited_states<4>(P, G, st, vsP, vsG, nx, ny, R(0), gamma, alpha_mp, beta_mp, PL, PR);
+    } else
         direct_states<4>(P, G, st, vsP, vsG, PL, PR);
     PL[3] = R(0);
     PR[3] = R(0);
@@ -132,8 +140,12 @@ __device__ __forceinline__ bool face_flux_2d(const R *P, const R *G, int st, int
            isfinite(phi[4]);
 }
 
+// FP64: at least three workgroups per CU where the LDS allows it (the
+// 16 x 16 tile; 168 VGPRs with an 8-byte spill); the other tiles are held
+// at two by their LDS either way
 template <int TX, int TY, bool LIM, class R>
-__global__ void __launch_bounds__(kBlock) k_batch_stage(BatchArgs a, int stage, double ca, double cb)
+__global__ void __launch_bounds__(kBlock, sizeof(R) == 8 ? 3 : 1)
+    k_batch_stage(BatchArgs a, int stage, double ca, double cb)
 {
     static_assert(TX * TY == kBlock, "one cell per thread");
     constexpr int PXS = TX + 12, PYS = TY + 12;  // pencil lengths (6-cell halo)
