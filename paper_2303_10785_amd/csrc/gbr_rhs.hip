@@ -10,11 +10,12 @@
 //                   Ducros sensor; LDS-tiled in (i, j) with a register window
 //                   along k.
 //   k_sweep<D>    : per direction D, a tile of interfaces along D: primitive
-//                   pencils staged in LDS with a 6-cell halo and E6 first
+//                   pencils staged in LDS with a 6-cell halo, E6 first
+//                   derivatives and (see kCurvLds) the Hermite second
 //                   derivatives formed once per cell in LDS; one thread per
-//                   interface forms the Hermite second derivatives it needs,
-//                   the characteristic (limited) or direct van Leer states,
-//                   HLLC and the alpha-damping viscous flux. The fluxes go
+//                   interface forms the characteristic (limited) or direct
+//                   van Leer states, HLLC and the alpha-damping viscous
+//                   flux. The fluxes go
 //                   back to LDS and each cell accumulates
 //                   -(Phi(+1/2) - Phi(-1/2)) into Res (written by the first
 //                   sweep, zeta in 3-D and eta in 2-D, updated by the others;
@@ -26,8 +27,8 @@
 // Precision: the RHS kernels are templated on the compute type R. FP64 runs
 // everything in double. FP32-bulk (R = float) keeps primitives, gradients,
 // the sensor, the reconstruction, limiter, HLLC, viscous flux and Res in
-// float, while Q, the metrics, J and (1/J)_t stay in double and the RK stage
-// accumulates in double.
+// float and reads the metrics from a float copy of the double ones, while
+// Q, J and (1/J)_t stay in double and the RK stage accumulates in double.
 #include <algorithm>
 #include <type_traits>
 
