@@ -140,11 +140,11 @@ __device__ __forceinline__ bool face_flux_2d(const R *P, const R *G, int st, int
            isfinite(phi[4]);
 }
 
-// FP64: at least three workgroups per CU where the LDS allows it (the
-// 16 x 16 tile; 168 VGPRs with an 8-byte spill); the other tiles are held
-// at two by their LDS either way
+// FP64 16 x 16 tiles: at least three workgroups per CU (168 VGPRs with an
+// 8-byte spill); the FP64 32 x 8 and 8 x 32 tiles are held at two by their
+// LDS either way
 template <int TX, int TY, bool LIM, class R>
-__global__ void __launch_bounds__(kBlock, sizeof(R) == 8 ? 3 : 1)
+__global__ void __launch_bounds__(kBlock, (sizeof(R) == 8 && TX == TY) ? 3 : 1)
     k_batch_stage(BatchArgs a, int stage, double ca, double cb)
 {
     static_assert(TX * TY == kBlock, "one cell per thread");
