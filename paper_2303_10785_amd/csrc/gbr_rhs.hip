@@ -883,7 +883,8 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     if (own && MODE == 2) {
         dt = *a.dt;
         J = a.m[GBR_SLOT_CELL_J * N + ch];
-        it = a.m[GBR_SLOT_CELL_INVJT * N + ch];
+        // (1/J)_t is zero on static grids and not read there
+        it = a.moving ? a.m[GBR_SLOT_CELL_INVJT * N + ch] : 0.0;
         if (a.sigma) {
             sg = a.sigma[ch];
             vj = a.m[GBR_SLOT_CELL_INVJ * N + ch];
