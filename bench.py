@@ -68,16 +68,16 @@ ALG_BYTES_PER_CELL_RHS = alg_bytes_per_cell_rhs()  # 440 B: 3-D NS, FP64, static
 # counter traffic; the headline roofline uses the algorithmic bytes above.
 IMPL_BYTES_PER_CELL = {
     "prims": 40 + 48,                     # Q -> rho, u, v, w, p, T
-    "cell_grad": 32 + 72 + 96 + 8,        # u, v, w, T, 9 cell metrics -> 12 gradients, theta
+    "cell_grad": 32 + 72 + 96 + 1,        # u, v, w, T, 9 cell metrics -> 12 gradients, sensor flag
     # the sweeps run zeta, eta, xi: zeta writes Res, eta adds to it, and xi,
     # last, applies the SSP-RK3 stage
-    "sweep_zeta": 48 + 96 + 64 + 8 + 8 + 40,  # 5 primitives + T, 12 face metrics, 8 tangential
-                                              # grads, T', theta -> Res out
-    "sweep_eta": 48 + 96 + 64 + 8 + 8 + 80,   # ... Res in and out
+    "sweep_zeta": 48 + 96 + 64 + 8 + 1 + 40,  # 5 primitives + T, 12 face metrics, 8 tangential
+                                              # grads, T', sensor flag -> Res out
+    "sweep_eta": 48 + 96 + 64 + 8 + 1 + 80,   # ... Res in and out
     # with the stage fused: Res in; Q, Qn, J in ((1/J)_t too on moving
     # grids); Q out; the next stage's primitives out in two of the three
     # stages
-    "sweep_xi": 48 + 96 + 64 + 8 + 8 + 40 + 88 + 40 + (2 * 48) / 3,
+    "sweep_xi": 48 + 96 + 64 + 8 + 1 + 40 + 88 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     # gbr_step forms the first stage's primitives in the time-step pass
     "cfl": 40 + 72 + 48,                  # Q, 9 cell metrics (temporal ones: moving grids only) -> primitives

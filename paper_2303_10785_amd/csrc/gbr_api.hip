@@ -115,10 +115,10 @@ size_t bytes_for(const gbr_config *c)
 {
     size_t N = (size_t)c->n[0] * c->n[1] * c->n[2];
     size_t nv = (size_t)c->ndim + 2;
-    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 1 + 12 + 2 * nv + (c->scheme == GBR_SCHEME_MIG4 ? 6 : 0)) + 1 +
+    size_t doubles = N * (GBR_SLOT_COUNT + 12 + 12 + 2 * nv + (c->scheme == GBR_SCHEME_MIG4 ? 6 : 0)) + 1 +
                      gbr::kReducePartials;
     const size_t floats = (c->precision == GBR_FP32_BULK) ? N * gbr::kFloatMetricSlots : 0;
-    return doubles * sizeof(double) + floats * sizeof(float) + sizeof(unsigned long long) + 2 * sizeof(int);
+    return doubles * sizeof(double) + floats * sizeof(float) + N + sizeof(unsigned long long) + 2 * sizeof(int);
 }
 
 gbr_status fail(gbr_grid_s *g, gbr_status s, const char *msg)
@@ -152,7 +152,7 @@ void release(gbr_grid_s *g)
     drop_records(g);
     for (hipEvent_t e : g->pool) (void)hipEventDestroy(e);
     g->pool.clear();
-    for (void *p : {(void *)g->metrics, (void *)g->metrics_f, (void *)g->scratch, (void *)g->theta,
+    for (void *p : {(void *)g->metrics, (void *)g->metrics_f, (void *)g->scratch, (void *)g->lim_flag,
                     (void *)g->grad2, (void *)g->prim, (void *)g->prim2, (void *)g->sigma,
                     (void *)g->partial, (void *)g->qn,
                     (void *)g->res, (void *)g->dt, (void *)g->dtmin, (void *)g->flags})
@@ -204,7 +204,7 @@ gbr_status gbr_grid_create(const gbr_config *cfg, void *hip_stream, gbr_grid *ou
     alloc((void **)&g->metrics, N * GBR_SLOT_COUNT * sizeof(double));
     if (cfg->precision == GBR_FP32_BULK) alloc((void **)&g->metrics_f, N * gbr::kFloatMetricSlots * sizeof(float));
     alloc((void **)&g->scratch, N * 12 * sizeof(double));
-    alloc((void **)&g->theta, N * sizeof(double));
+    alloc((void **)&g->lim_flag, N);
     if (cfg->scheme == GBR_SCHEME_MIG4) alloc((void **)&g->grad2, N * 6 * sizeof(double));
     alloc((void **)&g->prim, N * 6 * sizeof(double));
     alloc((void **)&g->prim2, N * 6 * sizeof(double));

@@ -443,17 +443,16 @@ __global__ void __launch_bounds__(kBlock) k_bc_state(Dims dm, Slab s, BcTypes bt
     for (int v = 0; v < NV; ++v) Q[v * N + gc] = q[v];
 }
 
-// Ghost sensor values of the slab of one bounded direction: the value of
-// the nearest interior cell (clamped along every bounded direction, so a
+// Ghost sensor flags of the slab of one bounded direction: the flag of the
+// nearest interior cell (clamped along every bounded direction, so a
 // corner ghost visited by two slabs gets the same value from both).
-template <class R>
-__global__ void __launch_bounds__(kBlock) k_theta_ghosts(Dims dm, Slab s, R *theta)
+__global__ void __launch_bounds__(kBlock) k_flag_ghosts(Dims dm, Slab s, unsigned char *flag)
 {
     const long e = blockIdx.x * (long)kBlock + threadIdx.x;
     if (e >= s.count) return;
     int t[3], side, depth;
     slab_cell(dm, s, e, t, &side, &depth);
-    theta[pack(dm, t)] = theta[clamp_to(dm, t, -1)];
+    flag[pack(dm, t)] = flag[clamp_to(dm, t, -1)];
 }
 
 struct QRef {
@@ -546,8 +545,7 @@ hipError_t launch_bc_state(gbr_grid_s *g, double *Q)
     return hipGetLastError();
 }
 
-template <class R>
-hipError_t launch_theta_ghosts(gbr_grid_s *g, R *theta)
+hipError_t launch_flag_ghosts(gbr_grid_s *g, unsigned char *flag)
 {
     const Dims dm = dims_of(g);
     Timed timed(g, GBR_K_CELL_GRAD);
@@ -555,7 +553,7 @@ hipError_t launch_theta_ghosts(gbr_grid_s *g, R *theta)
         if (g->cfg.bc[d][0] == GBR_BC_PERIODIC) continue;
         const Slab s = slab_of(dm, d);
         const unsigned blocks = unsigned((s.count + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL((k_theta_ghosts<R>), dim3(blocks), dim3(kBlock), 0, g->stream, dm, s, theta);
+        hipLaunchKernelGGL(k_flag_ghosts, dim3(blocks), dim3(kBlock), 0, g->stream, dm, s, flag);
     }
     return hipGetLastError();
 }
@@ -578,8 +576,6 @@ hipError_t launch_sponge(gbr_grid_s *g, const double *Q, R *res)
 
 template hipError_t launch_bc_prims<double>(gbr_grid_s *, double *, const double *);
 template hipError_t launch_bc_prims<float>(gbr_grid_s *, float *, const double *);
-template hipError_t launch_theta_ghosts<double>(gbr_grid_s *, double *);
-template hipError_t launch_theta_ghosts<float>(gbr_grid_s *, float *);
 template hipError_t launch_sponge<double>(gbr_grid_s *, const double *, double *);
 template hipError_t launch_sponge<float>(gbr_grid_s *, const double *, float *);
 

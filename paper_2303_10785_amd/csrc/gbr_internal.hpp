@@ -22,7 +22,7 @@ struct gbr_grid_s {
     // after each metric evaluation
     float *metrics_f = nullptr;
     double *scratch = nullptr;   // 12 * ncell: coordinate derivatives (metrics) / gradients (rhs)
-    double *theta = nullptr;     // ncell: shock sensor
+    unsigned char *lim_flag = nullptr;  // ncell: 1 where the Ducros sensor exceeds theta_c
     double *grad2 = nullptr;     // 6 * ncell, MIG4 only: IG4 gradients of rho and p, (d * 2 + s)
     double *prim = nullptr;      // 6 * ncell: rho, u, v, w, p, T of the state being differentiated
     double *prim2 = nullptr;     // 6 * ncell: second primitive buffer (gbr_step stages alternate)
@@ -159,8 +159,7 @@ hipError_t launch_metrics_bounded(gbr_grid_s *g, const double *xyz);
 template <class R>
 hipError_t launch_bc_prims(gbr_grid_s *g, R *prim, const double *Q);
 hipError_t launch_bc_state(gbr_grid_s *g, double *Q);
-template <class R>
-hipError_t launch_theta_ghosts(gbr_grid_s *g, R *theta);
+hipError_t launch_flag_ghosts(gbr_grid_s *g, unsigned char *flag);
 template <class R>
 hipError_t launch_sponge(gbr_grid_s *g, const double *Q, R *res);
 hipError_t launch_fill(gbr_grid_s *g, double *p, long n, double value);

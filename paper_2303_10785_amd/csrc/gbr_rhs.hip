@@ -7,7 +7,7 @@
 //                   and the positivity / finiteness check of the state.
 //   k_cell_grad   : per cell, E6 gradients of (u, v, w, T) along xi, eta,
 //                   zeta (kept for the tangential viscous terms) and the
-//                   Ducros sensor; LDS-tiled in (i, j) with a register window
+//                   Ducros sensor flag; LDS-tiled in (i, j) with a register window
 //                   along k.
 //   k_sweep<D>    : per direction D, a tile of interfaces along D: primitive
 //                   pencils staged in LDS with a 6-cell halo, E6 first
@@ -101,7 +101,7 @@ struct RhsArgs {
     R *res;
     R *grad;       // 12 * ncell: (d * 4 + s), s = u, v, w, T
     R *grad2;      // 6 * ncell (MIG4): (d * 2 + s), s = rho, p
-    R *theta;      // ncell
+    unsigned char *flag;  // ncell: 1 where the Ducros sensor exceeds theta_c
     R *prim;       // 6 * ncell: rho, u, v, w, p, T
     const double *m;  // metrics (always double)
     const R *mr;      // the metrics the flux kernels read in the compute type:
@@ -175,6 +175,9 @@ __global__ void __launch_bounds__(kBlock) k_prims(RhsArgs<R> a)
 // the paper): theta = div^2 /
 // (div^2 + |curl|^2 + 1e-30) of the physical velocity gradient
 // G[a][b] = sum_d (d_{x_b}) du_a/dd from the computational gradients gd[d][a].
+// The kernels keep one byte per cell, theta > theta_c, in the compute type;
+// an interface is limited when either of its cells is flagged, which is the
+// same decision as max(theta_a, theta_b) > theta_c.
 template <class R>
 __device__ __forceinline__ void load_unhat(const R *m, long N, long idx, R mt[3][3])
 {
@@ -475,7 +478,7 @@ __global__ void __launch_bounds__(kBlock) k_sensor(RhsArgs<R> a)
         for (int q = 0; q < 4; ++q) gd[d][q] = (d < NDIM) ? a.grad[(d * 4 + q) * N + idx] : R(0);
     R mt[3][3];
     load_unhat(a.mr, N, idx, mt);
-    a.theta[idx] = ducros_theta(gd, mt);
+    a.flag[idx] = ducros_theta(gd, mt) > a.pr.theta_c;
 }
 
 // Gradient tile: GI x GJ cells in the (i, j) plane, marching KC planes along
@@ -573,7 +576,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_grad(RhsArgs<R> a)
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int s = 0; s < 4; ++s) a.grad[(d * 4 + s) * N + idx] = gd[d][s];
-            if (SENSOR) a.theta[idx] = ducros_theta(gd, mt);
+            if (SENSOR) a.flag[idx] = ducros_theta(gd, mt) > a.pr.theta_c;
         }
         __syncthreads();
         if (NDIM == 3) {
@@ -719,7 +722,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         const int cg0 = min(c0 + cl0, nc - 1);
         const long a0 = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t0 - 1, ns), cg0, o);
         const long b0 = cell_of(dm, T::SD, T::CD, wrap_if(edge, s0 + t0, ns), cg0, o);
-        const bool mine = fmax(a.theta[a0], a.theta[b0]) > ph.theta_c;
+        const bool mine = (a.flag[a0] | a.flag[b0]) != 0;
         const unsigned long long bal = __ballot(mine);
         const int lane = tid % 64, wave = tid / 64;
         const int below = __popcll(bal & ((1ull << lane) - 1ull));
@@ -748,7 +751,7 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
     const R *Ga = s1 + T::at(t + 2, cl, N1);
     const R *Ha = kCurvLds<D, R> ? s2 + T::at(t + 1, cl, N2) : Pa;
     const R *m = a.mr;
-    if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = fmax(a.theta[ca], a.theta[cb]) > ph.theta_c;
+    if (!compact && ph.limiter == GBR_LIM_DUCROS) limited = (a.flag[ca] | a.flag[cb]) != 0;
     // In the eta and zeta sweeps the interface metrics are requested before
     // the unlimited states are formed, so their latency overlaps that work
     // (the limited path reads them after the limiter, whose register peak
@@ -1298,7 +1301,7 @@ hipError_t rhs_all(gbr_grid_s *g, const RhsArgs<R> &a, bool prims = true, bool f
             hipLaunchKernelGGL((k_cell_grad<NDIM, false, R>), gg, dim3(kBlock), 0, g->stream, a);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (g->bounded && a.pr.limiter == GBR_LIM_DUCROS && (e = launch_theta_ghosts<R>(g, a.theta)) != hipSuccess)
+    if (g->bounded && a.pr.limiter == GBR_LIM_DUCROS && (e = launch_flag_ghosts(g, a.flag)) != hipSuccess)
         return e;
     if ((e = sweeps<NDIM, VISC, R, false>(g, a, fuse_rk)) != hipSuccess) return e;
     // the sponge of a plain RHS (the fused stage applies it itself)
@@ -1319,7 +1322,7 @@ RhsArgs<R> make_args(gbr_grid_s *g, const double *Q, R *res)
     a.res = res;
     a.grad = reinterpret_cast<R *>(g->scratch);
     a.grad2 = reinterpret_cast<R *>(g->grad2);
-    a.theta = reinterpret_cast<R *>(g->theta);
+    a.flag = g->lim_flag;
     a.prim = reinterpret_cast<R *>(g->prim);
     a.m = g->metrics;
     if constexpr (std::is_same<R, float>::value)
