@@ -71,13 +71,14 @@ IMPL_BYTES_PER_CELL = {
     "cell_grad": 32 + 72 + 96 + 1,        # u, v, w, T, 9 cell metrics -> 12 gradients, sensor flag
     # the sweeps run zeta, eta, xi: zeta writes Res, eta adds to it, and xi,
     # last, applies the SSP-RK3 stage
-    "sweep_zeta": 48 + 96 + 64 + 8 + 1 + 40,  # 5 primitives + T, 12 face metrics, 8 tangential
-                                              # grads, T', sensor flag -> Res out
-    "sweep_eta": 48 + 96 + 64 + 8 + 1 + 80,   # ... Res in and out
+    "sweep_zeta": 40 + 96 + 64 + 8 + 1 + 40,  # 5 primitives (T formed from rho, p), 12 face
+                                              # metrics, 8 tangential grads, T', sensor flag
+                                              # -> Res out
+    "sweep_eta": 40 + 96 + 64 + 8 + 1 + 80,   # ... Res in and out
     # with the stage fused: Res in; Q, Qn, J in ((1/J)_t too on moving
     # grids); Q out; the next stage's primitives out in two of the three
     # stages
-    "sweep_xi": 48 + 96 + 64 + 8 + 1 + 40 + 88 + 40 + (2 * 48) / 3,
+    "sweep_xi": 40 + 96 + 64 + 8 + 1 + 40 + 88 + 40 + (2 * 48) / 3,
     "rk_stage": 40 + 80 + 40 + 8 + 8,     # Qn, Q in/out, Res, J, (1/J)_t
     # gbr_step forms the first stage's primitives in the time-step pass
     "cfl": 40 + 72 + 48,                  # Q, 9 cell metrics (temporal ones: moving grids only) -> primitives

@@ -801,8 +801,20 @@ __device__ __forceinline__ void sweep_tile(const RhsArgs<R> &a, int s_begin, int
         // Step-1: interface gradients of (u, v, w, T) along each computational
         // direction; the normal one from Eq. AD-eqn1 (beta_D = 0), tangential
         // ones from the average of the two cell gradients.
-        R c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], Tc[ca]};
-        R c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], Tc[cb]};
+        // T of the two cells: in FP64 from their density and pressure in LDS
+        // (T = gM2 p / rho, as the primitives kernel forms it) rather than
+        // read, 8 bytes per cell less; FP32-bulk reads the float T stored
+        // from the double evaluation
+        R ta, tb;
+        if constexpr (sizeof(R) == 8) {
+            ta = ph.gM2 * Pa[4 * VP] * (R(1) / Pa[0]);
+            tb = ph.gM2 * Pa[4 * VP + st] * (R(1) / Pa[st]);
+        } else {
+            ta = Tc[ca];
+            tb = Tc[cb];
+        }
+        R c0v[4] = {Pa[VP], Pa[2 * VP], Pa[3 * VP], ta};
+        R c1v[4] = {Pa[VP + st], Pa[2 * VP + st], Pa[3 * VP + st], tb};
         R g0[4] = {Ga[V1], Ga[2 * V1], Ga[3 * V1], gr[(D * 4 + 3) * N + ca]};
         R g1[4] = {Ga[V1 + st], Ga[2 * V1 + st], Ga[3 * V1 + st], gr[(D * 4 + 3) * N + cb]};
         R sL[4], sR[4], gf[3][4];
